@@ -1,0 +1,187 @@
+"""Pins of the CPU oracle against brute force, closed forms and invariants the
+method fixes (numerical exactness, symmetry of the auxiliary matrix, interface
+continuity, reciprocity, special cases)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from oracle.dd_oracle import ldl_solve_dense
+from paper_2002_05019_amd import problem as P
+from tests.conftest import cached_case
+
+
+def _spec(name, **kw):
+    s = P.named_spec(name)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+@pytest.fixture(scope="module")
+def c6():
+    return cached_case("cube6")
+
+
+@pytest.fixture(scope="module")
+def dd6(c6):
+    return oracle.serial_dd(c6)
+
+
+def test_global_solve_matches_dense_bruteforce(c6):
+    u_lu = oracle.global_solve(c6.A, c6.f)
+    u_dense = oracle.dense_solve(c6.A, c6.f)
+    assert oracle.rel_error(u_lu, u_dense).max() < 1e-12
+
+
+def test_arrowhead_bruteforce_equals_global(c6, dd6):
+    """The torn saddle-point system of the paper's decomposed problem has the
+    undecomposed FEM solution as its (owner-copy) primal part."""
+    M, rhs = oracle.arrowhead(c6)
+    x = oracle.dense_solve(M, rhs)
+    nt = sum(d.n for d in c6.domains)
+    u_ref = oracle.dense_solve(c6.A, c6.f)
+    assert oracle.rel_error(c6.owner_copy(x[:nt]), u_ref).max() < 1e-12
+    # the serial DD (FETI-like reduction) reaches the same primal and dual unknowns
+    assert oracle.rel_error(dd6["u"], x[:nt]).max() < 1e-12
+    assert oracle.rel_error(dd6["lam"], x[nt:]).max() < 1e-11
+
+
+@pytest.mark.parametrize("name", ["cube6", "cube12", "cube18u"])
+def test_serial_dd_is_numerically_exact(name):
+    c = cached_case(name)
+    out = oracle.serial_dd(c)
+    u_ref = oracle.global_solve(c.A, c.f)
+    assert oracle.rel_error(c.owner_copy(out["u"]), u_ref).max() < 1e-11
+    # continuity of every duplicated edge
+    off, acc = 0, np.zeros((c.n_mult, c.spec.nrhs), complex)
+    for i, d in enumerate(c.domains):
+        acc += c.B(i) @ out["u"][off:off + d.n]
+        off += d.n
+    assert np.linalg.norm(acc) <= 1e-12 * np.linalg.norm(out["u"])
+    r, rl = oracle.torn_residual(c, out["u"], out["lam"])
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(c.f)
+    assert oracle.global_residual(c, out["u"]).max() < 1e-12
+
+
+def test_aux_matrix_symmetric_not_hermitian_block_sparse(c6, dd6):
+    F = dd6["F"].toarray()
+    nF = np.abs(F).max()
+    assert np.abs(F - F.T).max() <= 1e-14 * nF          # self-adjoint reduction: F = F^T
+    assert np.abs(F - F.conj().T).max() > 1e-3 * nF     # lossy media: complex symmetric only
+    # block-wise sparsity = union of the domains' cliques on their multipliers
+    dom_sets = [set(c6.imap_mult[c6.imap_ptr[i]:c6.imap_ptr[i + 1]].tolist()) for i in range(c6.n_dom)]
+    clique = np.zeros_like(F, dtype=bool)
+    for s in dom_sets:
+        idx = np.array(sorted(s))
+        clique[np.ix_(idx, idx)] = True
+    assert not np.any(np.abs(F[~clique]) > 0)
+    assert np.all(np.abs(F[clique]) > 0)
+    assert clique.mean() < 0.5
+
+
+def test_interface_inverse_bruteforce(c6):
+    """(K^-1)_GG via SuperLU = dense inverse, = inverse of the dense interface
+    Schur complement K_GG - K_GI K_II^-1 K_IG."""
+    for i in (0, 5):
+        K = c6.domains[i].K.toarray()
+        g = c6.gamma(i)
+        X, _ = oracle.interface_inverse(c6.domains[i].K, g)
+        Xd = np.linalg.inv(K)[np.ix_(g, g)]
+        assert np.abs(X - Xd).max() <= 1e-12 * np.abs(Xd).max()
+        I = np.setdiff1d(np.arange(K.shape[0]), g)
+        S = K[np.ix_(g, g)] - K[np.ix_(g, I)] @ np.linalg.solve(K[np.ix_(I, I)], K[np.ix_(I, g)])
+        assert np.abs(np.linalg.inv(S) - X).max() <= 1e-11 * np.abs(X).max()
+        # D_i = B_i K_i^-1 B_i^T
+        mids, D, _ = oracle.dual_blocks(c6, i)
+        Bi = c6.B(i).toarray()[mids]
+        assert np.abs(Bi @ np.linalg.inv(K) @ Bi.T - D).max() <= 1e-12 * np.abs(D).max()
+
+
+def test_robin_parameter_invariance():
+    """The Robin magnitude changes K_i and F but not the solution."""
+    us, Fs = [], []
+    for beta in (0.5, 1.0, 2.0):
+        c = P.make_case(_spec("cube6", beta=beta))
+        out = oracle.serial_dd(c)
+        us.append(c.owner_copy(out["u"]))
+        Fs.append(out["F"].toarray())
+    for u in us[1:]:
+        assert oracle.rel_error(u, us[0]).max() < 1e-10
+    assert np.abs(Fs[0] - Fs[2]).max() > 1e-3 * np.abs(Fs[0]).max()
+
+
+def test_constraint_choice_invariance():
+    """Star and chain multipliers on cross-line edges give the same primal
+    solution (different multipliers)."""
+    a = P.make_case(_spec("cube6"))
+    b = P.make_case(_spec("cube6", constraints="chain"))
+    oa, ob = oracle.serial_dd(a), oracle.serial_dd(b)
+    assert oracle.rel_error(ob["u"], oa["u"]).max() < 1e-11
+    assert np.abs(oa["lam"] - ob["lam"]).max() > 1e-6
+
+
+def test_single_domain_reduces_to_sparse_direct():
+    c = P.make_case(_spec("cube6", cuts=((0, 6),) * 3))
+    assert c.n_mult == 0 and c.n_dom == 1
+    out = oracle.serial_dd(c)
+    assert oracle.rel_error(out["u"], oracle.dense_solve(c.A, c.f)).max() < 1e-12
+
+
+def test_two_domains_dense_aux_bunch_kaufman():
+    """Two domains: F is one dense complex-symmetric block; a Bunch-Kaufman
+    LDL^T (LAPACK zsytrf) solve gives the same multipliers as LU."""
+    c = P.make_case(_spec("cube6", cuts=((0, 3, 6), (0, 6), (0, 6))))
+    out = oracle.serial_dd(c)
+    F = out["F"].toarray()
+    assert np.all(np.abs(F) > 0)
+    lam_bk = ldl_solve_dense(F, out["d"])
+    assert oracle.rel_error(lam_bk, out["lam"]).max() < 1e-12
+    u_ref = oracle.dense_solve(c.A, c.f)
+    assert oracle.rel_error(c.owner_copy(out["u"]), u_ref).max() < 1e-12
+
+
+def test_reciprocity_and_linearity(c6):
+    """A = A^T: u2^T f1 = u1^T f2; and the solve is linear."""
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((c6.n_global, 2)) + 1j * rng.standard_normal((c6.n_global, 2))
+    # torn split of arbitrary global f: lowest-id owner gets the value
+    seen = np.zeros(c6.n_global, bool)
+    ft = []
+    for d in c6.domains:
+        new = ~seen[d.l2g]
+        blk = np.zeros((d.n, 2), complex)
+        blk[new] = f[d.l2g[new]]
+        seen[d.l2g] = True
+        ft.append(blk)
+    u = c6.owner_copy(oracle.serial_dd(c6, F_rhs=ft)["u"])
+    assert abs(u[:, 1] @ f[:, 0] - u[:, 0] @ f[:, 1]) <= 1e-12 * np.abs(u).max() * np.abs(f).sum()
+    a, b = 0.3 - 1.2j, 2.0 + 0.5j
+    ft2 = [np.stack([a * x[:, 0] + b * x[:, 1]], 1) for x in ft]
+    u2 = c6.owner_copy(oracle.serial_dd(c6, F_rhs=ft2)["u"])
+    assert oracle.rel_error(u2[:, 0], a * u[:, 0] + b * u[:, 1]).max() < 1e-12
+
+
+def test_planted_mistakes_are_caught(c6, monkeypatch):
+    """A conjugate instead of a plain transpose, or a dropped sign in B^T lam,
+    must break the pins above (checked here on the oracle, CPU only)."""
+    import oracle.dd_oracle as od
+    u_ref = oracle.dense_solve(c6.A, c6.f)
+    real_dual = od.dual_blocks
+
+    def conj_dual(case, i, lu=None):
+        m, D, lu = real_dual(case, i, lu)
+        return m, D.conj(), lu
+    monkeypatch.setattr(od, "dual_blocks", conj_dual)
+    bad = od.serial_dd(c6)
+    assert oracle.rel_error(c6.owner_copy(bad["u"]), u_ref).max() > 1e-6
+    monkeypatch.setattr(od, "dual_blocks", real_dual)
+    # a sign slip in the interface map
+    c_bad = cached_case("cube6")
+    sign = c_bad.imap_sign.copy()
+    try:
+        c_bad.imap_sign[::7] *= -1
+        bad = od.serial_dd(c_bad)
+        assert oracle.rel_error(c_bad.owner_copy(bad["u"]), u_ref).max() > 1e-6
+    finally:
+        c_bad.imap_sign[:] = sign
