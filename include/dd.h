@@ -1,0 +1,189 @@
+/*
+ * dd.h - C ABI of the MI355X direct domain-decomposition (DD) FEM solver.
+ *
+ * Method (Moshfegh & Vouvakis, "Direct Solution of FEM Models: Are Sparse
+ * Direct Solvers the Best Strategy?", section II): a decomposed FEM problem
+ * with primal DoFs inside every domain and dual DoFs (Lagrange multipliers) on
+ * the interfaces forms the arrowhead system
+ *
+ *      [ blkdiag(K_i)  B^T ] [ u      ]   [ f ]
+ *      [ B             0   ] [ lambda ] = [ 0 ]
+ *
+ * with complex-symmetric domain matrices K_i (K_i = K_i^T, not Hermitian) and
+ * a signed Boolean interface operator B.  The solver
+ *   1. eliminates the primal DoFs of every domain by independent sparse LDL^T
+ *      factorisations (multifrontal, batched across domains on the GPU),
+ *   2. forms each domain's dual interface block B_i K_i^-1 B_i^T,
+ *   3. assembles and factors the block-sparse symmetric auxiliary matrix
+ *      F = sum_i B_i K_i^-1 B_i^T with a block LDL^T using restricted
+ *      Bunch-Kaufman pivoting (symbolic phase on the clique graph of the
+ *      domains), and
+ *   4. recovers the primal unknowns for many right-hand sides by independent
+ *      forward/backward substitutions u_i = K_i^-1 (f_i - B_i^T lambda).
+ *
+ * Threading: a context may be used by one host thread at a time.  Every entry
+ * point returns a dd_status and never throws; the message of the last failure
+ * of the calling thread is returned by dd_last_error().
+ *
+ * Memory: the library never allocates device memory.  The caller allocates a
+ * device workspace of dd_workspace_size() bytes (for example a torch uint8
+ * tensor) and binds it with dd_bind_workspace().  Host state is owned by the
+ * context and released by dd_destroy().
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One complex FP64 value; layout-compatible with std::complex<double>,
+ * C99 double _Complex and torch.complex128. */
+typedef struct { double re, im; } dd_z;
+
+typedef struct dd_ctx_s *dd_ctx;
+
+typedef enum {
+    DD_OK = 0,
+    DD_ERR_ARG = -1,           /* null pointer, negative size, bad option            */
+    DD_ERR_PATTERN = -2,       /* malformed CSR pattern                              */
+    DD_ERR_MAP = -3,           /* malformed interface map                            */
+    DD_ERR_STATE = -4,         /* call out of order (e.g. solve before factor)       */
+    DD_ERR_NOMEM = -5,         /* workspace too small / host allocation failed       */
+    DD_ERR_SINGULAR = -6,      /* a pivot block had to be perturbed (see dd_info)    */
+    DD_ERR_NUMERIC = -7,       /* NaN/Inf met during factor or solve                 */
+    DD_ERR_NOT_CONVERGED = -8, /* refinement hit refine_maxit above refine_tol      */
+    DD_ERR_DEVICE = -9         /* a HIP runtime call failed                          */
+} dd_status;
+
+enum { DD_FP64 = 0, DD_FP32_REFINE = 1 };
+
+/* Sparsity pattern of one domain matrix K_i (host memory).
+ * Square n x n, CSR, 0-based, both triangles stored (structurally symmetric),
+ * column indices strictly increasing within a row, every diagonal present. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *rowptr;   /* [n+1], rowptr[0] = 0, rowptr[n] = nnz */
+    const int32_t *colind;   /* [nnz] */
+} dd_pattern;
+
+/* The decomposed problem (host memory; deep-copied by dd_setup).
+ * Interface map: the entries of domain i are [imap_ptr[i], imap_ptr[i+1]);
+ * entry e says row imap_mult[e] of B has value imap_sign[e] (+1 or -1) in
+ * column imap_dof[e] of domain i.  Every multiplier id in [0, n_mult) must
+ * appear in exactly two entries, belonging to two different domains. */
+typedef struct {
+    int32_t n_dom;
+    const dd_pattern *dom;     /* [n_dom] */
+    int64_t n_mult;
+    const int64_t *imap_ptr;   /* [n_dom+1] */
+    const int32_t *imap_dof;   /* [imap_ptr[n_dom]] local dof in the domain   */
+    const int64_t *imap_mult;  /* [imap_ptr[n_dom]] multiplier id             */
+    const int8_t  *imap_sign;  /* [imap_ptr[n_dom]] +1 / -1                    */
+    const float   *dof_xyz;    /* optional [sum n_i][3] coordinates that steer
+                                  the nested-dissection orderings (any embedding,
+                                  e.g. logical lattice positions); may be NULL,
+                                  then a graph-only ordering is used            */
+} dd_problem;
+
+typedef struct {
+    int32_t precision;     /* DD_FP64, or DD_FP32_REFINE: complex FP32 fronts,
+                              Schur updates and substitutions, FP64 pivot blocks,
+                              FP64 residuals and refinement updates             */
+    double  refine_tol;    /* DD_FP32_REFINE: stop when every column has
+                              ||r|| / ||f|| <= refine_tol (default 1e-9)        */
+    int32_t refine_maxit;  /* DD_FP32_REFINE: iteration cap (default 20)        */
+    int32_t max_rhs;       /* columns per internal solve block; the workspace is
+                              sized for it, larger nrhs are solved in blocks
+                              (default 64)                                       */
+    int32_t leaf_size;     /* nested-dissection leaf size (default 48)          */
+    int32_t use_graph;     /* reserved, must be 0                               */
+    int32_t verbose;       /* print the symbolic summary to stderr              */
+} dd_options;
+
+typedef struct {
+    double  t_setup;        /* host seconds in dd_setup                         */
+    double  t_factor;       /* device seconds of the last dd_factor             */
+    double  t_solve;        /* device seconds of the last dd_solve              */
+    double  flops_factor;   /* algorithmic real flops of one factorisation
+                               (complex FMA = 8), from the symbolic structure   */
+    double  flops_solve;    /* algorithmic real flops of one solve per RHS      */
+    double  bytes_factor;   /* bytes of the stored factors (L panels + inverse
+                               interface blocks) in the factor precision        */
+    int64_t workspace_bytes;
+    int32_t n_fronts_domain;
+    int32_t n_fronts_aux;
+    int32_t max_front_aux;
+    int32_t max_front_domain;
+    int32_t refine_iters;   /* refinement iterations of the last dd_solve       */
+    double  rel_resid;      /* max over columns of ||r||/||f|| (refined solves) */
+    int32_t n_perturbed;    /* pivot blocks perturbed in the last dd_factor     */
+    int32_t numeric_flags;  /* nonzero if NaN/Inf was met                       */
+} dd_info;
+
+/* Defaults listed above. */
+void dd_default_options(dd_options *opt);
+
+/* Symbolic phase, host only (no GPU call): validates the problem, orders every
+ * domain by nested dissection with its interface DoFs last, builds the
+ * multifrontal trees, groups the multipliers into blocks with identical domain
+ * pairs, orders the block (clique) graph of the auxiliary matrix, and plans the
+ * workspace and every launch.  opt may be NULL (defaults).
+ * Errors: DD_ERR_ARG, DD_ERR_PATTERN, DD_ERR_MAP, DD_ERR_NOMEM. */
+dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out);
+
+/* Bytes of device workspace the context needs (host only). */
+dd_status dd_workspace_size(dd_ctx ctx, int64_t *bytes);
+
+/* Binds caller-owned device memory (>= dd_workspace_size bytes, 256-byte
+ * aligned) and uploads the static index tables into it (synchronous copy on
+ * the current device).  The memory must stay allocated until dd_destroy or
+ * the next bind.  Errors: DD_ERR_NOMEM (too small), DD_ERR_DEVICE. */
+dd_status dd_bind_workspace(dd_ctx ctx, void *dev_ptr, int64_t bytes);
+
+/* Numeric factorisation, enqueued on hip_stream (a hipStream_t; NULL = the
+ * null stream).  vals: device array of the values of all domain matrices
+ * concatenated in domain order, nnz_i each in the CSR order of dd_setup's
+ * patterns.  The values are read during the call's stream work only (FP32
+ * mode keeps an FP64 copy in the workspace for refinement).
+ * Returns after enqueueing; numerical problems (perturbed pivots, NaN) are
+ * reported by dd_get_info and by the status of the next dd_solve. */
+dd_status dd_factor(dd_ctx ctx, const dd_z *vals, void *hip_stream);
+
+/* Solves the arrowhead system for nrhs right-hand sides.
+ * f: device, torn right-hand sides, column-major with leading dimension ldf
+ *    >= sum n_i; rows of domain i start at sum_{j<i} n_j.
+ * u: device output in the same layout (ldu >= sum n_i); may not alias f.
+ * lam: optional device output of the multipliers, n_mult x nrhs column-major
+ *    with leading dimension ldl >= n_mult (NULL to skip).
+ * FP32 mode refines in FP64 until refine_tol (DD_ERR_NOT_CONVERGED if the cap
+ * is hit; u and lam still hold the last iterate).  FP64 mode is asynchronous
+ * on hip_stream; FP32 mode synchronises the stream once per refinement step. */
+dd_status dd_solve(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u,
+                   int64_t ldu, dd_z *lam, int64_t ldl, void *hip_stream);
+
+/* Statistics; synchronises the streams of the last factor/solve. */
+dd_status dd_get_info(dd_ctx ctx, dd_info *info);
+
+/* Interface DoFs of domain dom in the order used by dd_get_interface_inverse
+ * (ascending local dof).  dofs may be NULL to query the count only. */
+dd_status dd_get_interface_dofs(dd_ctx ctx, int32_t dom, int32_t *count, int32_t *dofs);
+
+/* Copies (K_dom^-1) restricted to the interface DoFs, i.e. the inverse of the
+ * interface Schur complement, as a dense count x count column-major complex
+ * FP64 matrix into device memory out (after dd_factor, stream-ordered). */
+dd_status dd_get_interface_inverse(dd_ctx ctx, int32_t dom, dd_z *out, void *hip_stream);
+
+/* Releases the context (host state only; the workspace stays caller-owned). */
+void dd_destroy(dd_ctx ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD_H */

@@ -1,0 +1,294 @@
+// C ABI of the DD solver: argument checking, context, workspace binding and
+// the drivers of the numeric phases (see include/dd.h for the contract).
+#include <hip/hip_runtime_api.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+thread_local std::string g_err;
+
+dd_status fail(dd_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+}  // namespace
+
+struct dd_ctx_s {
+  dd::Plan plan;
+  dd_options opt;
+  uint8_t *ws = nullptr;
+  int64_t ws_bytes = 0;
+  bool factored = false;
+  bool events = false;
+  hipEvent_t ev[4];
+  bool fact_rec = false, solve_rec = false;
+  hipStream_t last = nullptr;
+  double t_setup = 0;
+  int refine_iters = 0;
+  double rel_resid = 0;
+};
+
+#define HIPCHECK(x)                                                                                \
+  do {                                                                                             \
+    hipError_t e_ = (x);                                                                           \
+    if (e_ != hipSuccess) return fail(DD_ERR_DEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+void dd_default_options(dd_options *o) {
+  if (!o) return;
+  o->precision = DD_FP64;
+  o->refine_tol = 1e-9;
+  o->refine_maxit = 20;
+  o->max_rhs = 64;
+  o->leaf_size = 48;
+  o->use_graph = 0;
+  o->verbose = 0;
+}
+
+const char *dd_last_error(void) { return g_err.c_str(); }
+
+dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
+  try {
+    g_err.clear();
+    if (!out) return fail(DD_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!prob) return fail(DD_ERR_ARG, "problem is null");
+    dd_options o;
+    dd_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != DD_FP64 && o.precision != DD_FP32_REFINE) return fail(DD_ERR_ARG, "unknown precision");
+    if (o.max_rhs < 1 || o.max_rhs > 4096) return fail(DD_ERR_ARG, "max_rhs must be in [1, 4096]");
+    if (o.leaf_size < 1) return fail(DD_ERR_ARG, "leaf_size must be >= 1");
+    if (o.refine_maxit < 0) return fail(DD_ERR_ARG, "refine_maxit must be >= 0");
+    if (!(o.refine_tol > 0)) return fail(DD_ERR_ARG, "refine_tol must be > 0");
+    if (o.use_graph != 0) return fail(DD_ERR_ARG, "use_graph is reserved and must be 0");
+    if (prob->n_dom < 1 || !prob->dom) return fail(DD_ERR_ARG, "need at least one domain");
+    auto t0 = std::chrono::steady_clock::now();
+    dd::ProblemView pv;
+    pv.n_dom = prob->n_dom;
+    pv.n_mult = prob->n_mult;
+    for (int i = 0; i < prob->n_dom; ++i) {
+      pv.n.push_back(prob->dom[i].n);
+      pv.rowptr.push_back(prob->dom[i].rowptr);
+      pv.colind.push_back(prob->dom[i].colind);
+      pv.nnz.push_back(prob->dom[i].nnz);
+    }
+    pv.imap_ptr = prob->imap_ptr;
+    pv.imap_dof = prob->imap_dof;
+    pv.imap_mult = prob->imap_mult;
+    pv.imap_sign = prob->imap_sign;
+    pv.xyz = prob->dof_xyz;
+    int code = 0;
+    std::string m = dd::validate_problem(pv, &code);
+    if (!m.empty()) return fail((dd_status)code, m);
+    dd::SetupOptions so;
+    so.precision = o.precision;
+    so.max_rhs = o.max_rhs;
+    so.leaf = o.leaf_size;
+    so.verbose = o.verbose;
+    dd_ctx_s *c = new dd_ctx_s;
+    m = dd::build_plan(pv, so, c->plan);
+    if (!m.empty()) {
+      delete c;
+      return fail(DD_ERR_PATTERN, m);
+    }
+    c->opt = o;
+    c->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = c;
+    return DD_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(DD_ERR_ARG, e.what());
+  }
+}
+
+dd_status dd_workspace_size(dd_ctx c, int64_t *bytes) {
+  if (!c || !bytes) return fail(DD_ERR_ARG, "null argument");
+  *bytes = c->plan.b_total;
+  return DD_OK;
+}
+
+dd_status dd_bind_workspace(dd_ctx c, void *dev, int64_t bytes) {
+  if (!c || !dev) return fail(DD_ERR_ARG, "null argument");
+  if (bytes < c->plan.b_total) return fail(DD_ERR_NOMEM, "workspace smaller than dd_workspace_size");
+  if (((uintptr_t)dev) & 255) return fail(DD_ERR_ARG, "workspace must be 256-byte aligned");
+  HIPCHECK(hipMemcpy((uint8_t *)dev + c->plan.b_meta, c->plan.meta.data(), c->plan.meta.size(),
+                     hipMemcpyHostToDevice));
+  if (!c->events) {
+    for (int i = 0; i < 4; ++i) HIPCHECK(hipEventCreate(&c->ev[i]));
+    c->events = true;
+  }
+  c->ws = (uint8_t *)dev;
+  c->ws_bytes = bytes;
+  c->factored = false;
+  return DD_OK;
+}
+
+dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  if (!c->ws) return fail(DD_ERR_STATE, "no workspace bound");
+  if (!vals && c->plan.nnz_total > 0) return fail(DD_ERR_ARG, "vals is null");
+  hipStream_t st = (hipStream_t)stream;
+  const void *v = vals;
+  if (c->plan.precision != 0) {
+    // FP64 copy of the operator for the refinement residuals
+    HIPCHECK(hipMemcpyAsync(c->ws + c->plan.b_vals, vals, c->plan.nnz_total * 16, hipMemcpyDeviceToDevice, st));
+    v = c->ws + c->plan.b_vals;
+  }
+  HIPCHECK(hipEventRecord(c->ev[0], st));
+  HIPCHECK(dd::factor(c->plan, c->ws, v, st));
+  HIPCHECK(hipEventRecord(c->ev[1], st));
+  c->fact_rec = true;
+  c->factored = true;
+  c->last = st;
+  return DD_OK;
+}
+
+dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, int64_t ldu, dd_z *lam, int64_t ldl,
+                   void *stream) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  if (!c->factored) return fail(DD_ERR_STATE, "dd_solve before dd_factor");
+  if (nrhs < 0) return fail(DD_ERR_ARG, "nrhs < 0");
+  if (nrhs == 0) return DD_OK;
+  const dd::Plan &P = c->plan;
+  if (!f || !u) return fail(DD_ERR_ARG, "f or u is null");
+  if (ldf < P.n_torn || ldu < P.n_torn) return fail(DD_ERR_ARG, "leading dimension below the torn size");
+  if (lam && ldl < P.n_mult) return fail(DD_ERR_ARG, "ldl below n_mult");
+  if ((const void *)f == (const void *)u) return fail(DD_ERR_ARG, "u may not alias f");
+  hipStream_t st = (hipStream_t)stream;
+  c->last = st;
+  HIPCHECK(hipEventRecord(c->ev[2], st));
+  dd_status result = DD_OK;
+  c->refine_iters = 0;
+  c->rel_resid = 0;
+  for (int32_t j0 = 0; j0 < nrhs; j0 += P.max_rhs) {
+    const int nb = std::min<int32_t>(P.max_rhs, nrhs - j0);
+    const dd_z *fj = f + (int64_t)j0 * ldf;
+    dd_z *uj = u + (int64_t)j0 * ldu;
+    dd_z *lj = lam ? lam + (int64_t)j0 * ldl : nullptr;
+    HIPCHECK(dd::rhs_in(P, c->ws, fj, ldf, nb, st));
+    HIPCHECK(dd::solve_core(P, c->ws, nb, false, st));
+    if (P.precision == 0) {
+      HIPCHECK(dd::sol_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
+      continue;
+    }
+    // FP64 iterative refinement with the FP32 factors
+    std::vector<double> fn(nb), rn(nb);
+    double *r64 = (double *)(c->ws + P.b_r64);
+    HIPCHECK(dd::refine_init(P, c->ws, nb, st));
+    HIPCHECK(dd::refine_resid(P, c->ws, fj, ldf, nb, true, st));
+    HIPCHECK(hipMemcpyAsync(fn.data(), r64 + P.r_fnorm, nb * 8, hipMemcpyDeviceToHost, st));
+    int it = 0;
+    double rel = 0;
+    for (;;) {
+      HIPCHECK(dd::refine_resid(P, c->ws, fj, ldf, nb, false, st));
+      HIPCHECK(hipMemcpyAsync(rn.data(), r64 + P.r_norm, nb * 8, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      rel = 0;
+      bool bad = false;
+      for (int j = 0; j < nb; ++j) {
+        double r = fn[j] > 0 ? std::sqrt(rn[j] / fn[j]) : std::sqrt(rn[j]);
+        if (!std::isfinite(r)) bad = true;
+        rel = std::max(rel, r);
+      }
+      if (bad) {
+        result = DD_ERR_NUMERIC;
+        g_err = "non-finite residual during refinement";
+        break;
+      }
+      if (rel <= c->opt.refine_tol) break;
+      if (it >= c->opt.refine_maxit) {
+        result = DD_ERR_NOT_CONVERGED;
+        g_err = "refinement did not reach refine_tol";
+        break;
+      }
+      HIPCHECK(dd::solve_core(P, c->ws, nb, true, st));
+      HIPCHECK(dd::refine_update(P, c->ws, nb, st));
+      ++it;
+    }
+    HIPCHECK(dd::refine_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
+    c->refine_iters = std::max(c->refine_iters, it);
+    c->rel_resid = std::max(c->rel_resid, rel);
+  }
+  HIPCHECK(hipEventRecord(c->ev[3], st));
+  c->solve_rec = true;
+  return result;
+}
+
+dd_status dd_get_info(dd_ctx c, dd_info *info) {
+  if (!c || !info) return fail(DD_ERR_ARG, "null argument");
+  std::memset(info, 0, sizeof *info);
+  const dd::Plan &P = c->plan;
+  info->t_setup = c->t_setup;
+  info->flops_factor = P.flops_factor;
+  info->flops_solve = P.flops_solve_rhs;
+  info->bytes_factor = P.bytes_factor;
+  info->workspace_bytes = P.b_total;
+  info->n_fronts_domain = P.n_front_dom;
+  info->n_fronts_aux = P.n_front_aux;
+  info->max_front_aux = P.max_front_aux;
+  info->max_front_domain = P.max_front_dom;
+  info->refine_iters = c->refine_iters;
+  info->rel_resid = c->rel_resid;
+  if (c->events) {
+    float ms = 0;
+    if (c->fact_rec) {
+      HIPCHECK(hipEventSynchronize(c->ev[1]));
+      HIPCHECK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+      info->t_factor = ms * 1e-3;
+    }
+    if (c->solve_rec) {
+      HIPCHECK(hipEventSynchronize(c->ev[3]));
+      HIPCHECK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+      info->t_solve = ms * 1e-3;
+    }
+  }
+  if (c->ws && c->factored) {
+    int st[2] = {0, 0};
+    HIPCHECK(hipStreamSynchronize(c->last));
+    HIPCHECK(hipMemcpy(st, c->ws + P.b_status, sizeof st, hipMemcpyDeviceToHost));
+    info->n_perturbed = st[0];
+    info->numeric_flags = st[1];
+  }
+  return DD_OK;
+}
+
+dd_status dd_get_interface_dofs(dd_ctx c, int32_t dom, int32_t *count, int32_t *dofs) {
+  if (!c || !count) return fail(DD_ERR_ARG, "null argument");
+  if (dom < 0 || dom >= c->plan.n_dom) return fail(DD_ERR_ARG, "domain out of range");
+  const auto &g = c->plan.gamma[dom];
+  *count = (int32_t)g.size();
+  if (dofs) std::memcpy(dofs, g.data(), g.size() * sizeof(int32_t));
+  return DD_OK;
+}
+
+dd_status dd_get_interface_inverse(dd_ctx c, int32_t dom, dd_z *out, void *stream) {
+  if (!c || !out) return fail(DD_ERR_ARG, "null argument");
+  if (dom < 0 || dom >= c->plan.n_dom) return fail(DD_ERR_ARG, "domain out of range");
+  if (!c->factored) return fail(DD_ERR_STATE, "no factorisation");
+  int f = c->plan.gamma_front[dom];
+  if (f < 0) return fail(DD_ERR_ARG, "domain has no interface");
+  HIPCHECK(dd::interface_inverse_out(c->plan, c->ws, f, out, (hipStream_t)stream));
+  return DD_OK;
+}
+
+void dd_destroy(dd_ctx c) {
+  if (!c) return;
+  if (c->events)
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+}  // extern "C"

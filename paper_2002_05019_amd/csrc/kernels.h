@@ -1,0 +1,29 @@
+// Host entry points of the HIP kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace dd {
+
+// numeric factorisation (enqueue only)
+hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st);
+// torn right-hand sides (interleaved complex FP64, ld ldf) -> internal vector
+hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, hipStream_t st);
+// one DD solve of the internal right-hand side (with_c: constraint rhs in vc)
+hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st);
+// internal solution / multipliers -> interleaved complex FP64
+hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
+                   hipStream_t st);
+hipError_t interface_inverse_out(const Plan &P, uint8_t *ws, int front, void *out, hipStream_t st);
+// FP64 iterative refinement around the FP32 factorisation
+hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st);
+hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st);
+hipError_t refine_resid(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, bool fnorm,
+                        hipStream_t st);
+hipError_t refine_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
+                      hipStream_t st);
+
+}  // namespace dd

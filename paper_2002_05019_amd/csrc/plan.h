@@ -1,0 +1,125 @@
+// Host-side plan of the DD solver: symbolic structure, workspace layout and
+// the launch sequences of the numeric phases.  Built once by dd_setup on the
+// CPU (no GPU call), then uploaded into the caller's workspace.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+enum LaunchKind : int32_t {
+  // factorisation
+  L_ASM,        // pull extend-add: assign children update blocks (zero elsewhere)
+  L_SCAT,       // add original domain-matrix entries
+  L_AUXG,       // add interface-inverse blocks into auxiliary fronts
+  L_PANEL,      // pivot-tile LDL^T with restricted Bunch-Kaufman
+  L_TRSM,       // W = A21 P L11^-T, L21 = W D^-1
+  L_SYRK,       // trailing update C -= L21 W^T
+  L_INVPREP,    // W' = P L21 L11^-1
+  L_INVTRMM,    // Z21 = -Z22 W'
+  L_INVSYRK,    // X = P^T Z^T D^-1 Z P
+  // solve
+  S_FINIT, S_FDIAG, S_FUPD, S_FFIN,
+  S_GEMV,       // interface: out = a*X*in + add
+  S_MGATHER,    // d = sum_i B_i y_i - c
+  S_HGATHER,    // h = B_Gamma^T lambda
+  S_BINIT, S_BPART, S_BDIAG, S_BFIN,
+};
+
+struct Launch {
+  int32_t kind;
+  int32_t count;     // number of items / workgroups
+  int64_t first;     // first item in the kind's item array
+  int32_t p0, p1;    // kind-specific
+};
+
+struct Plan {
+  // ---- problem
+  int32_t n_dom = 0;
+  int64_t n_mult = 0, n_torn = 0, nnz_total = 0;
+  std::vector<int32_t> dom_n;
+  std::vector<int64_t> dom_row;      // first torn row of each domain
+  std::vector<int64_t> dom_nnz;      // first value index of each domain
+  std::vector<int64_t> csr_ptr;      // torn system CSR (global rows/cols), n_torn + 1
+  std::vector<int32_t> csr_col;
+  std::vector<std::vector<int32_t>> gamma;   // sorted interface dofs per domain
+  std::vector<int32_t> gamma_front;          // interface-root front id per domain (-1 if none)
+
+  // ---- fronts
+  std::vector<FrontDev> fronts;
+  std::vector<int32_t> vars;
+  std::vector<int32_t> child_front;
+  std::vector<int64_t> child_rmap;
+  std::vector<int32_t> rmap;
+  std::vector<SPair> spairs;
+  std::vector<AuxItem> aux_items;
+  std::vector<int32_t> gpos, gsign;
+  std::vector<MultRef> mrefs;
+  std::vector<GamRef> grefs;
+  std::vector<int32_t> hmult, hsign;
+  std::vector<int32_t> row_gam;
+
+  // ---- schedule
+  std::vector<Item> items;
+  std::vector<Launch> factor_seq;
+  std::vector<Launch> solve_dom_fwd;   // interior forward + Gamma assemble
+  std::vector<Launch> solve_aux;       // aux forward + backward
+  std::vector<Launch> solve_dom_bwd;   // Gamma scatter + interior backward
+  std::vector<Item> gemv_items;        // interface GEMV items (one per 64-row tile)
+  int64_t max_partials = 0;            // partial slots needed by S_BPART (per launch)
+
+  // ---- options / layout
+  int32_t precision = 0;
+  int32_t max_rhs = 64;
+  size_t elem = 8;                     // sizeof(T)
+  int64_t t_elems = 0;                 // T elements in the numeric region
+  int64_t vf_off = 0, vx_off = 0, vd_off = 0, vl_off = 0, vc_off = 0, part_off = 0;
+  int64_t side_n = 0;                  // fully-summed positions (side arrays)
+  // byte offsets inside the workspace
+  int64_t b_meta = 0, b_num = 0, b_side = 0, b_vals = 0, b_r64 = 0, b_status = 0, b_total = 0;
+  // offsets (bytes) of each meta array inside the meta blob
+  int64_t m_fronts, m_vars, m_cfront, m_crmap, m_rmap, m_spairs, m_aux, m_gpos, m_gsign,
+      m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_csrc;
+  std::vector<uint8_t> meta;           // serialised meta blob
+  // FP64 refinement vectors (doubles, planar) inside the r64 region
+  int64_t r_u = 0, r_l = 0, r_ru = 0, r_rl = 0, r_norm = 0, r_fnorm = 0, r_part = 0;
+  int64_t r_nblk = 0;
+
+  // ---- statistics
+  double flops_factor = 0, flops_solve_rhs = 0, bytes_factor = 0;
+  int32_t n_front_dom = 0, n_front_aux = 0, max_front_dom = 0, max_front_aux = 0;
+};
+
+struct SetupOptions {
+  int32_t precision = 0;
+  int32_t max_rhs = 64;
+  int32_t leaf = 48;
+  int32_t aux_leaf = 256;
+  int32_t verbose = 0;
+};
+
+struct ProblemView {
+  int32_t n_dom;
+  int64_t n_mult;
+  std::vector<int32_t> n;
+  std::vector<const int64_t *> rowptr;
+  std::vector<const int32_t *> colind;
+  std::vector<int64_t> nnz;
+  const int64_t *imap_ptr;
+  const int32_t *imap_dof;
+  const int64_t *imap_mult;
+  const int8_t *imap_sign;
+  const float *xyz;
+};
+
+// Validates the problem; returns an empty string or the error message and
+// sets *code to the dd_status value.
+std::string validate_problem(const ProblemView &p, int *code);
+
+// Builds the full plan (symbolic analysis, schedule, workspace layout).
+std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &plan);
+
+}  // namespace dd

@@ -1,0 +1,1115 @@
+// Symbolic phase of the DD solver (host only, no GPU call).
+//
+// * Domain matrices: nested-dissection ordering of the interior DoFs with the
+//   interface DoFs (those carrying a multiplier) eliminated last, as the root
+//   front; multifrontal tree, update-row sets and extend-add maps.
+// * Auxiliary matrix F = sum_i B_i K_i^-1 B_i^T (paper, section II): its
+//   nonzero structure is the union of one clique per domain on the domain's
+//   multipliers.  Multipliers shared by the same pair of domains are
+//   indistinguishable, so they are grouped into blocks; the symbolic
+//   factorisation runs on the (much smaller) block graph and every front is a
+//   union of whole dense blocks.
+// * The launch schedule of the numeric phases and the workspace layout.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <utility>
+
+#include "plan.h"
+
+namespace dd {
+
+// ----------------------------------------------------------------------------
+// validation
+std::string validate_problem(const ProblemView &p, int *code) {
+  char buf[512];
+  *code = -1;
+  if (p.n_dom < 1) return "n_dom must be >= 1";
+  if (p.n_mult < 0) return "n_mult must be >= 0";
+  if (p.n_mult > 0x3fffffff) return "n_mult too large";
+  for (int i = 0; i < p.n_dom; ++i) {
+    const int32_t n = p.n[i];
+    if (n < 0) { snprintf(buf, sizeof buf, "domain %d: negative size", i); return buf; }
+    if (!p.rowptr[i] || (p.nnz[i] > 0 && !p.colind[i])) {
+      snprintf(buf, sizeof buf, "domain %d: null pattern pointer", i);
+      return buf;
+    }
+    *code = -2;
+    const int64_t *rp = p.rowptr[i];
+    const int32_t *ci = p.colind[i];
+    if (rp[0] != 0 || rp[n] != p.nnz[i]) {
+      snprintf(buf, sizeof buf, "domain %d: rowptr[0] must be 0 and rowptr[n] = nnz", i);
+      return buf;
+    }
+    std::vector<int64_t> cnt(n, 0);
+    for (int32_t r = 0; r < n; ++r) {
+      if (rp[r + 1] < rp[r]) { snprintf(buf, sizeof buf, "domain %d: rowptr decreases at row %d", i, r); return buf; }
+      bool diag = false;
+      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+        int32_t c = ci[e];
+        if (c < 0 || c >= n) { snprintf(buf, sizeof buf, "domain %d: column %d out of range in row %d", i, c, r); return buf; }
+        if (e > rp[r] && ci[e - 1] >= c) { snprintf(buf, sizeof buf, "domain %d: columns not strictly increasing in row %d", i, r); return buf; }
+        if (c == r) diag = true;
+        cnt[c]++;
+      }
+      if (!diag) { snprintf(buf, sizeof buf, "domain %d: missing diagonal in row %d", i, r); return buf; }
+    }
+    for (int32_t r = 0; r < n; ++r) {
+      if (cnt[r] != rp[r + 1] - rp[r]) { snprintf(buf, sizeof buf, "domain %d: pattern not symmetric (row %d)", i, r); return buf; }
+      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+        int32_t c = ci[e];
+        if (!std::binary_search(ci + rp[c], ci + rp[c + 1], r)) {
+          snprintf(buf, sizeof buf, "domain %d: pattern not symmetric (%d,%d)", i, r, c);
+          return buf;
+        }
+      }
+    }
+  }
+  *code = -3;
+  if (p.n_mult > 0 && (!p.imap_ptr || !p.imap_dof || !p.imap_mult || !p.imap_sign))
+    return "interface map pointers must be non-null";
+  if (!p.imap_ptr) return p.n_mult == 0 ? (*code = 0, std::string()) : std::string("null imap_ptr");
+  if (p.imap_ptr[0] != 0) return "imap_ptr[0] must be 0";
+  std::vector<int32_t> mcnt(p.n_mult, 0), mdom(p.n_mult, -1);
+  for (int i = 0; i < p.n_dom; ++i) {
+    if (p.imap_ptr[i + 1] < p.imap_ptr[i]) return "imap_ptr decreases";
+    for (int64_t e = p.imap_ptr[i]; e < p.imap_ptr[i + 1]; ++e) {
+      int32_t d = p.imap_dof[e];
+      int64_t m = p.imap_mult[e];
+      int s = p.imap_sign[e];
+      if (d < 0 || d >= p.n[i]) { snprintf(buf, sizeof buf, "interface entry %lld: dof %d out of range for domain %d", (long long)e, d, i); return buf; }
+      if (m < 0 || m >= p.n_mult) { snprintf(buf, sizeof buf, "interface entry %lld: multiplier %lld out of range", (long long)e, (long long)m); return buf; }
+      if (s != 1 && s != -1) { snprintf(buf, sizeof buf, "interface entry %lld: sign must be +1 or -1", (long long)e); return buf; }
+      if (mdom[m] == i) { snprintf(buf, sizeof buf, "multiplier %lld appears twice in domain %d", (long long)m, i); return buf; }
+      mdom[m] = i;
+      mcnt[m]++;
+    }
+  }
+  for (int64_t m = 0; m < p.n_mult; ++m)
+    if (mcnt[m] != 2) {
+      snprintf(buf, sizeof buf, "multiplier %lld has %d entries (needs exactly 2)", (long long)m, mcnt[m]);
+      return buf;
+    }
+  *code = 0;
+  return std::string();
+}
+
+// ----------------------------------------------------------------------------
+// nested dissection on a CSR graph (self loops ignored)
+namespace {
+
+struct NdGraph {
+  int n = 0;
+  const int64_t *ptr = nullptr;
+  const int32_t *col = nullptr;
+  const double *xyz = nullptr;   // 3 per vertex or null
+  const double *w = nullptr;     // vertex weights or null (= 1)
+};
+
+struct NdTree {
+  std::vector<std::vector<int>> vars;
+  std::vector<std::vector<int>> kids;
+  int add(std::vector<int> v, std::vector<int> k) {
+    vars.push_back(std::move(v));
+    kids.push_back(std::move(k));
+    return (int)vars.size() - 1;
+  }
+};
+
+class Dissector {
+ public:
+  Dissector(const NdGraph &g, double leaf_w) : G(g), leaf(leaf_w), stamp(g.n, 0), side(g.n, 0), lev(g.n, -1) {}
+
+  std::vector<int> run(std::vector<int> &V, NdTree &T) {
+    double wV = weight(V);
+    if (V.size() <= 1 || wV <= leaf) return {T.add(V, {})};
+    std::vector<int> L, S, R;
+    bool ok = G.xyz && plane_split(V, L, S, R);
+    if (!ok) ok = level_split(V, L, S, R);
+    if (!ok) return {T.add(V, {})};
+    std::vector<int> kids;
+    if (!L.empty()) {
+      auto a = run(L, T);
+      kids.insert(kids.end(), a.begin(), a.end());
+    }
+    if (!R.empty()) {
+      auto b = run(R, T);
+      kids.insert(kids.end(), b.begin(), b.end());
+    }
+    if (S.empty()) return kids;
+    std::sort(S.begin(), S.end());
+    return {T.add(S, kids)};
+  }
+
+ private:
+  const NdGraph &G;
+  double leaf;
+  std::vector<int> stamp;
+  std::vector<int8_t> side;
+  std::vector<int> lev;
+  int cur = 0;
+
+  double wt(int v) const { return G.w ? G.w[v] : 1.0; }
+  double weight(const std::vector<int> &V) const {
+    double s = 0;
+    for (int v : V) s += wt(v);
+    return s;
+  }
+  void mark(const std::vector<int> &V) {
+    ++cur;
+    for (int v : V) stamp[v] = cur;
+  }
+
+  // Plane separator on the coordinates: the vertices lying exactly on an
+  // axis-aligned plane, if no edge crosses the plane.
+  bool plane_split(const std::vector<int> &V, std::vector<int> &L, std::vector<int> &S, std::vector<int> &R) {
+    mark(V);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int v : V)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], G.xyz[3 * v + a]);
+        hi[a] = std::max(hi[a], G.xyz[3 * v + a]);
+      }
+    int axes[3] = {0, 1, 2};
+    std::sort(axes, axes + 3, [&](int a, int b) { return hi[a] - lo[a] > hi[b] - lo[b]; });
+    const double wV = weight(V);
+    for (int ai = 0; ai < 3; ++ai) {
+      const int ax = axes[ai];
+      if (hi[ax] - lo[ax] <= 0) break;
+      std::vector<std::pair<double, double>> xs;  // (coord, weight)
+      xs.reserve(V.size());
+      for (int v : V) xs.push_back({G.xyz[3 * v + ax], wt(v)});
+      std::sort(xs.begin(), xs.end());
+      // cumulative weights at distinct values
+      std::vector<double> vals, wbelow, won;
+      double acc = 0;
+      for (size_t i = 0; i < xs.size();) {
+        size_t j = i;
+        double wo = 0;
+        while (j < xs.size() && xs[j].first == xs[i].first) wo += xs[j++].second;
+        vals.push_back(xs[i].first);
+        wbelow.push_back(acc);
+        won.push_back(wo);
+        acc += wo;
+        i = j;
+      }
+      // candidates: balanced planes, closest to the weighted median first
+      std::vector<std::pair<double, int>> cand;
+      for (size_t u = 0; u < vals.size(); ++u) {
+        double wl = wbelow[u], wr = wV - wbelow[u] - won[u];
+        if (wl >= 0.15 * wV && wr >= 0.15 * wV) cand.push_back({std::fabs(wl - wr) / wV, (int)u});
+      }
+      std::sort(cand.begin(), cand.end());
+      int best = -1;
+      double best_score = 1e300;
+      int tried = 0;
+      for (auto &c : cand) {
+        if (tried++ >= 8) break;
+        const double u = vals[c.second];
+        bool sep = true;
+        for (int v : V) {
+          if (G.xyz[3 * v + ax] >= u) continue;
+          for (int64_t e = G.ptr[v]; e < G.ptr[v + 1] && sep; ++e) {
+            int w = G.col[e];
+            if (w != v && stamp[w] == cur && G.xyz[3 * w + ax] > u) sep = false;
+          }
+          if (!sep) break;
+        }
+        if (!sep) continue;
+        double score = won[c.second] * (1.0 + c.first);
+        if (score < best_score) {
+          best_score = score;
+          best = c.second;
+        }
+      }
+      if (best >= 0) {
+        const double u = vals[best];
+        L.clear(); S.clear(); R.clear();
+        for (int v : V) {
+          double x = G.xyz[3 * v + ax];
+          (x < u ? L : (x > u ? R : S)).push_back(v);
+        }
+        return true;
+      }
+    }
+    return false;
+  }
+
+  int bfs(const std::vector<int> &V, int src, std::vector<int> &order) {
+    // BFS inside the marked set; lev[] holds levels; returns depth
+    order.clear();
+    for (int v : V) lev[v] = -1;
+    lev[src] = 0;
+    order.push_back(src);
+    for (size_t h = 0; h < order.size(); ++h) {
+      int v = order[h];
+      for (int64_t e = G.ptr[v]; e < G.ptr[v + 1]; ++e) {
+        int w = G.col[e];
+        if (stamp[w] == cur && lev[w] < 0) {
+          lev[w] = lev[v] + 1;
+          order.push_back(w);
+        }
+      }
+    }
+    return lev[order.back()];
+  }
+
+  // Level-set separator of a BFS from a pseudo-peripheral vertex.
+  bool level_split(const std::vector<int> &V, std::vector<int> &L, std::vector<int> &S, std::vector<int> &R) {
+    mark(V);
+    std::vector<int> order;
+    bfs(V, V[0], order);
+    L.clear(); S.clear(); R.clear();
+    if (order.size() < V.size()) {           // disconnected: split off one component
+      for (int v : V) (lev[v] >= 0 ? L : R).push_back(v);
+      return true;
+    }
+    int far = order.back();
+    for (int it = 0; it < 2; ++it) {
+      bfs(V, far, order);
+      far = order.back();
+    }
+    int D = lev[order.back()];
+    if (D < 2) return false;
+    std::vector<double> wl(D + 1, 0.0);
+    for (int v : V) wl[lev[v]] += wt(v);
+    const double wV = weight(V);
+    double below = 0;
+    int best = -1;
+    double best_score = 1e300;
+    for (int l = 0; l <= D; ++l) {
+      double after = wV - below - wl[l];
+      if (l >= 1 && l <= D - 1) {
+        double imb = std::fabs(below - after) / wV;
+        bool balanced = below >= 0.2 * wV && after >= 0.2 * wV;
+        double score = wl[l] * (1.0 + imb) + (balanced ? 0.0 : 1e200 * imb);
+        if (score < best_score) {
+          best_score = score;
+          best = l;
+        }
+      }
+      below += wl[l];
+    }
+    if (best < 0) return false;
+    for (int v : V) (lev[v] < best ? L : (lev[v] > best ? R : S)).push_back(v);
+    return true;
+  }
+};
+
+// Multifrontal symbolic factorisation of an elimination forest given by
+// NdTree nodes: postorder, ranks, and the update rows of every node.
+struct Symb {
+  std::vector<int> post;                  // node ids in postorder
+  std::vector<int> parent;                // per node
+  std::vector<int> rank;                  // per unit
+  std::vector<std::vector<int>> rows;     // per node, sorted by rank
+  std::vector<int> height;                // per node
+};
+
+void symbolic(const NdTree &T, const std::vector<int> &roots, int nunits, const int64_t *ptr,
+              const int32_t *col, Symb &S) {
+  const int nn = (int)T.vars.size();
+  S.parent.assign(nn, -1);
+  S.height.assign(nn, 0);
+  S.rows.assign(nn, {});
+  S.rank.assign(nunits, -1);
+  S.post.clear();
+  for (int v = 0; v < nn; ++v)
+    for (int k : T.kids[v]) S.parent[k] = v;
+  // iterative postorder
+  std::vector<std::pair<int, size_t>> st;
+  for (int r : roots) {
+    st.push_back({r, 0});
+    while (!st.empty()) {
+      auto &top = st.back();
+      if (top.second < T.kids[top.first].size()) {
+        int k = T.kids[top.first][top.second++];
+        st.push_back({k, 0});
+      } else {
+        S.post.push_back(top.first);
+        st.pop_back();
+      }
+    }
+  }
+  int rk = 0;
+  for (int v : S.post)
+    for (int u : T.vars[v]) S.rank[u] = rk++;
+  std::vector<int> stamp(nunits, -1);
+  for (int v : S.post) {
+    int maxr = -1;
+    for (int u : T.vars[v]) maxr = std::max(maxr, S.rank[u]);
+    std::vector<int> R;
+    auto consider = [&](int w) {
+      if (S.rank[w] > maxr && stamp[w] != v) {
+        stamp[w] = v;
+        R.push_back(w);
+      }
+    };
+    for (int u : T.vars[v])
+      for (int64_t e = ptr[u]; e < ptr[u + 1]; ++e) consider(col[e]);
+    int h = 0;
+    for (int k : T.kids[v]) {
+      for (int w : S.rows[k]) consider(w);
+      h = std::max(h, S.height[k] + 1);
+    }
+    S.height[v] = h;
+    std::sort(R.begin(), R.end(), [&](int a, int b) { return S.rank[a] < S.rank[b]; });
+    S.rows[v] = std::move(R);
+  }
+}
+
+inline int ntiles(int x, int t) { return (x + t - 1) / t; }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
+  P = Plan();
+  P.n_dom = p.n_dom;
+  P.n_mult = p.n_mult;
+  P.precision = o.precision;
+  P.max_rhs = o.max_rhs;
+  P.elem = o.precision == 0 ? sizeof(double) : sizeof(float);
+  P.dom_n.assign(p.n.begin(), p.n.end());
+  P.dom_row.resize(p.n_dom + 1);
+  P.dom_nnz.resize(p.n_dom + 1);
+  P.dom_row[0] = 0;
+  P.dom_nnz[0] = 0;
+  for (int i = 0; i < p.n_dom; ++i) {
+    P.dom_row[i + 1] = P.dom_row[i] + p.n[i];
+    P.dom_nnz[i + 1] = P.dom_nnz[i] + p.nnz[i];
+  }
+  P.n_torn = P.dom_row[p.n_dom];
+  P.nnz_total = P.dom_nnz[p.n_dom];
+  if (P.n_torn > 0x3fffffff) return "too many torn DoFs";
+
+  // torn-system CSR (for the FP64 residual of the refinement)
+  P.csr_ptr.resize(P.n_torn + 1);
+  P.csr_col.resize(P.nnz_total);
+  for (int i = 0; i < p.n_dom; ++i) {
+    for (int32_t r = 0; r <= p.n[i]; ++r) P.csr_ptr[P.dom_row[i] + r] = P.dom_nnz[i] + p.rowptr[i][r];
+    for (int64_t e = 0; e < p.nnz[i]; ++e) P.csr_col[P.dom_nnz[i] + e] = (int32_t)(P.dom_row[i] + p.colind[i][e]);
+  }
+
+  // interface dofs per domain (sorted) and the multiplier entries
+  P.gamma.assign(p.n_dom, {});
+  std::vector<int32_t> m_dom(2 * p.n_mult), m_dof(2 * p.n_mult), m_sg(2 * p.n_mult), m_fill(p.n_mult, 0);
+  for (int i = 0; i < p.n_dom; ++i) {
+    auto &g = P.gamma[i];
+    for (int64_t e = p.imap_ptr ? p.imap_ptr[i] : 0; e < (p.imap_ptr ? p.imap_ptr[i + 1] : 0); ++e) {
+      g.push_back(p.imap_dof[e]);
+      int64_t m = p.imap_mult[e];
+      int slot = m_fill[m]++;
+      m_dom[2 * m + slot] = i;
+      m_dof[2 * m + slot] = p.imap_dof[e];
+      m_sg[2 * m + slot] = p.imap_sign[e];
+    }
+    std::sort(g.begin(), g.end());
+    g.erase(std::unique(g.begin(), g.end()), g.end());
+  }
+  // order the two entries of each multiplier by domain
+  for (int64_t m = 0; m < p.n_mult; ++m)
+    if (m_dom[2 * m] > m_dom[2 * m + 1]) {
+      std::swap(m_dom[2 * m], m_dom[2 * m + 1]);
+      std::swap(m_dof[2 * m], m_dof[2 * m + 1]);
+      std::swap(m_sg[2 * m], m_sg[2 * m + 1]);
+    }
+  auto gpos_of = [&](int d, int dof) {
+    auto &g = P.gamma[d];
+    return (int32_t)(std::lower_bound(g.begin(), g.end(), dof) - g.begin());
+  };
+
+  // ------------------------------------------------------------ domain trees
+  struct FH {
+    int kind, dom, height, parent = -1;
+    std::vector<int> vars, rows, kids;
+  };
+  std::vector<FH> F;
+  std::vector<std::vector<int>> dom_fronts(p.n_dom);
+  P.gamma_front.assign(p.n_dom, -1);
+  std::vector<double> xyzd;
+  for (int i = 0; i < p.n_dom; ++i) {
+    const int n = p.n[i];
+    NdGraph G;
+    G.n = n;
+    G.ptr = p.rowptr[i];
+    G.col = p.colind[i];
+    if (p.xyz) {
+      xyzd.resize(3 * (size_t)n);
+      for (int64_t k = 0; k < 3 * (int64_t)n; ++k) xyzd[k] = p.xyz[3 * P.dom_row[i] + k];
+      G.xyz = xyzd.data();
+    }
+    std::vector<char> isg(n, 0);
+    for (int d : P.gamma[i]) isg[d] = 1;
+    std::vector<int> interior;
+    for (int v = 0; v < n; ++v)
+      if (!isg[v]) interior.push_back(v);
+    NdTree T;
+    Dissector D(G, (double)o.leaf);
+    std::vector<int> roots;
+    if (!interior.empty()) roots = D.run(interior, T);
+    if (!P.gamma[i].empty()) {
+      std::vector<int> g(P.gamma[i].begin(), P.gamma[i].end());
+      roots = {T.add(g, roots)};
+    }
+    Symb S;
+    symbolic(T, roots, n, p.rowptr[i], p.colind[i], S);
+    // verify the separator property: every child's update rows sit in its parent front
+    std::vector<int> id(T.vars.size());
+    for (int v : S.post) {
+      id[v] = (int)F.size();
+      FH f;
+      f.kind = (!P.gamma[i].empty() && v == roots[0]) ? FK_GAMMA : FK_INTERIOR;
+      f.dom = i;
+      f.height = S.height[v];
+      f.vars = T.vars[v];
+      f.rows = S.rows[v];
+      F.push_back(std::move(f));
+      dom_fronts[i].push_back(id[v]);
+    }
+    for (int v : S.post) {
+      for (int k : T.kids[v]) {
+        F[id[v]].kids.push_back(id[k]);
+        F[id[k]].parent = id[v];
+      }
+    }
+    if (!P.gamma[i].empty()) {
+      P.gamma_front[i] = id[roots[0]];
+      if (!F[id[roots[0]]].rows.empty()) return "internal: interface root has update rows";
+    }
+  }
+  const int n_dom_fronts = (int)F.size();
+
+  // ------------------------------------------------------------ aux block graph
+  std::map<std::pair<int, int>, int> bkey;
+  std::vector<std::vector<int32_t>> bmult;       // multipliers of each block
+  std::vector<std::array<int, 2>> bdom;
+  std::vector<int> mblock(p.n_mult);
+  for (int64_t m = 0; m < p.n_mult; ++m) {
+    auto key = std::make_pair(m_dom[2 * m], m_dom[2 * m + 1]);
+    auto it = bkey.find(key);
+    int b;
+    if (it == bkey.end()) {
+      b = (int)bmult.size();
+      bkey[key] = b;
+      bmult.push_back({});
+      bdom.push_back({key.first, key.second});
+    } else {
+      b = it->second;
+    }
+    bmult[b].push_back((int32_t)m);
+    mblock[m] = b;
+  }
+  const int nb = (int)bmult.size();
+  // block adjacency: share a domain
+  std::vector<std::vector<int>> dom_blocks(p.n_dom);
+  for (int b = 0; b < nb; ++b) {
+    dom_blocks[bdom[b][0]].push_back(b);
+    dom_blocks[bdom[b][1]].push_back(b);
+  }
+  std::vector<int64_t> bptr(nb + 1, 0);
+  std::vector<int32_t> bcol;
+  {
+    std::vector<int> st(nb, -1);
+    for (int b = 0; b < nb; ++b) {
+      for (int s = 0; s < 2; ++s)
+        for (int c : dom_blocks[bdom[b][s]])
+          if (st[c] != b) {
+            st[c] = b;
+            bcol.push_back(c);
+          }
+      bptr[b + 1] = (int64_t)bcol.size();
+    }
+  }
+  std::vector<double> bw(nb), bxyz;
+  for (int b = 0; b < nb; ++b) bw[b] = (double)bmult[b].size();
+  if (p.xyz) {
+    bxyz.assign(3 * (size_t)nb, 0.0);
+    for (int b = 0; b < nb; ++b) {
+      for (int32_t m : bmult[b]) {
+        int d = m_dom[2 * m], dof = m_dof[2 * m];
+        for (int a = 0; a < 3; ++a) bxyz[3 * b + a] += p.xyz[3 * (P.dom_row[d] + dof) + a];
+      }
+      for (int a = 0; a < 3; ++a) bxyz[3 * b + a] /= (double)bmult[b].size();
+    }
+  }
+  std::vector<int> aux_first(nb, 0);
+  if (nb > 0) {
+    NdGraph G;
+    G.n = nb;
+    G.ptr = bptr.data();
+    G.col = bcol.data();
+    G.xyz = p.xyz ? bxyz.data() : nullptr;
+    G.w = bw.data();
+    NdTree T;
+    Dissector D(G, (double)o.aux_leaf);
+    std::vector<int> all(nb);
+    std::iota(all.begin(), all.end(), 0);
+    std::vector<int> roots = D.run(all, T);
+    Symb S;
+    symbolic(T, roots, nb, bptr.data(), bcol.data(), S);
+    std::vector<int> id(T.vars.size());
+    for (int v : S.post) {
+      id[v] = (int)F.size();
+      FH f;
+      f.kind = FK_AUX;
+      f.dom = -1;
+      f.height = S.height[v];
+      f.vars = T.vars[v];      // block ids for now
+      f.rows = S.rows[v];
+      F.push_back(std::move(f));
+    }
+    for (int v : S.post)
+      for (int k : T.kids[v]) {
+        F[id[v]].kids.push_back(id[k]);
+        F[id[k]].parent = id[v];
+      }
+  }
+
+  // ------------------------------------------------------------ front descriptors
+  const int nf = (int)F.size();
+  P.fronts.resize(nf);
+  // block position bookkeeping for aux fronts: unit lists (blocks) kept aside
+  std::vector<std::vector<int>> aux_units(nf);
+  for (int f = 0; f < nf; ++f) {
+    FH &h = F[f];
+    FrontDev &d = P.fronts[f];
+    std::memset(&d, 0, sizeof d);
+    d.kind = h.kind;
+    d.dom = h.dom;
+    d.xoff = -1;
+    d.goff = -1;
+    d.idx = (int64_t)P.vars.size();
+    if (h.kind == FK_AUX) {
+      std::vector<int> units(h.vars);
+      units.insert(units.end(), h.rows.begin(), h.rows.end());
+      int s = 0;
+      for (int b : h.vars) s += (int)bmult[b].size();
+      int n = 0;
+      for (int b : units) {
+        for (int32_t m : bmult[b]) P.vars.push_back(m);
+        n += (int)bmult[b].size();
+      }
+      d.s = s;
+      d.n = n;
+      d.vbase = 0;
+      aux_units[f] = std::move(units);
+    } else {
+      d.s = (int)h.vars.size();
+      d.n = d.s + (int)h.rows.size();
+      for (int v : h.vars) P.vars.push_back(v);
+      for (int v : h.rows) P.vars.push_back(v);
+      d.vbase = P.dom_row[h.dom];
+    }
+    d.wcols = h.kind == FK_GAMMA ? 2 * NB : NB;
+  }
+  // children + reverse extend-add maps
+  {
+    std::vector<int32_t> pos;
+    for (int f = 0; f < nf; ++f) {
+      FrontDev &d = P.fronts[f];
+      d.child = (int64_t)P.child_front.size();
+      d.nchild = (int)F[f].kids.size();
+      if (d.nchild == 0) continue;
+      // position of every variable in this front
+      const int32_t *fv = &P.vars[d.idx];
+      std::map<int32_t, int32_t> small;
+      int32_t maxv = 0;
+      for (int r = 0; r < d.n; ++r) maxv = std::max(maxv, fv[r]);
+      pos.assign((size_t)maxv + 1, -1);
+      for (int r = 0; r < d.n; ++r) pos[fv[r]] = r;
+      for (int c : F[f].kids) {
+        const FrontDev &cd = P.fronts[c];
+        P.child_front.push_back(c);
+        P.child_rmap.push_back((int64_t)P.rmap.size());
+        size_t base = P.rmap.size();
+        P.rmap.resize(base + d.n, -1);
+        const int32_t *cv = &P.vars[cd.idx];
+        int prev = -1;
+        for (int j = cd.s; j < cd.n; ++j) {
+          int32_t v = cv[j];
+          int32_t pp = (v <= maxv) ? pos[v] : -1;
+          if (pp < 0) return "internal: update row missing in the parent front";
+          if (pp <= prev) return "internal: extend-add map not monotone";
+          prev = pp;
+          P.rmap[base + pp] = j - cd.s;
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------ original entries (domain fronts)
+  {
+    std::vector<int32_t> pos;
+    std::vector<int64_t> rank;
+    for (int i = 0; i < p.n_dom; ++i) {
+      // rank of every dof = position in the postorder concatenation of vars
+      rank.assign(p.n[i], -1);
+      int64_t rk = 0;
+      for (int f : dom_fronts[i]) {
+        const FrontDev &d = P.fronts[f];
+        for (int r = 0; r < d.s; ++r) rank[P.vars[d.idx + r]] = rk++;
+      }
+      if (rk != p.n[i]) return "internal: ordering does not cover the domain";
+      pos.assign(p.n[i], -1);
+      for (int f : dom_fronts[i]) {
+        FrontDev &d = P.fronts[f];
+        const int32_t *fv = &P.vars[d.idx];
+        for (int r = 0; r < d.n; ++r) pos[fv[r]] = r;
+        for (int c = 0; c < d.s; ++c) {
+          int32_t vc = fv[c];
+          for (int64_t e = p.rowptr[i][vc]; e < p.rowptr[i][vc + 1]; ++e) {
+            int32_t vr = p.colind[i][e];
+            if (rank[vr] < rank[vc]) continue;
+            int32_t pr = pos[vr];
+            if (pr < c) return "internal: original entry outside its front";
+            SPair sp;
+            sp.src = P.dom_nnz[i] + e;
+            sp.pos = pr + c * d.n;
+            sp.pad = 0;
+            P.spairs.push_back(sp);
+          }
+        }
+        for (int r = 0; r < d.n; ++r) pos[fv[r]] = -1;
+      }
+    }
+  }
+  // pair ranges per front (the pairs of a front are contiguous)
+  std::vector<std::pair<int64_t, int64_t>> prange(nf, {0, 0});
+  {
+    int64_t at = 0;
+    std::vector<int64_t> rank;
+    for (int i = 0; i < p.n_dom; ++i) {
+      rank.assign(p.n[i], -1);
+      int64_t rk = 0;
+      for (int f : dom_fronts[i]) {
+        const FrontDev &d = P.fronts[f];
+        for (int r = 0; r < d.s; ++r) rank[P.vars[d.idx + r]] = rk++;
+      }
+      for (int f : dom_fronts[i]) {
+        const FrontDev &d = P.fronts[f];
+        int64_t cnt = 0;
+        for (int c = 0; c < d.s; ++c) {
+          int32_t vc = P.vars[d.idx + c];
+          for (int64_t e = p.rowptr[i][vc]; e < p.rowptr[i][vc + 1]; ++e)
+            if (rank[p.colind[i][e]] >= rank[vc]) ++cnt;
+        }
+        prange[f] = {at, cnt};
+        at += cnt;
+      }
+    }
+    if (at != (int64_t)P.spairs.size()) return "internal: pair count mismatch";
+  }
+
+  // ------------------------------------------------------------ aux gather items
+  P.gpos.clear();
+  P.gsign.clear();
+  // per block and domain slot: offset of (gpos, gsign) arrays
+  std::vector<std::array<int64_t, 2>> boff(nb);
+  for (int b = 0; b < nb; ++b)
+    for (int s = 0; s < 2; ++s) {
+      boff[b][s] = (int64_t)P.gpos.size();
+      for (int32_t m : bmult[b]) {
+        int slot = (m_dom[2 * m] == bdom[b][s]) ? 0 : 1;
+        int d = m_dom[2 * m + slot];
+        P.gpos.push_back(gpos_of(d, m_dof[2 * m + slot]));
+        P.gsign.push_back(m_sg[2 * m + slot]);
+      }
+    }
+  std::vector<std::pair<int64_t, int64_t>> arange(nf, {0, 0});
+  for (int f = n_dom_fronts; f < nf; ++f) {
+    const auto &units = aux_units[f];
+    int nsep = (int)F[f].vars.size();
+    std::vector<int> upos(units.size());
+    int at = 0;
+    for (size_t u = 0; u < units.size(); ++u) {
+      upos[u] = at;
+      at += (int)bmult[units[u]].size();
+    }
+    int64_t first = (int64_t)P.aux_items.size();
+    for (int ia = 0; ia < nsep; ++ia) {
+      int a = units[ia];
+      for (size_t ib = ia; ib < units.size(); ++ib) {
+        int b = units[ib];
+        AuxItem it;
+        std::memset(&it, 0, sizeof it);
+        it.f = f;
+        it.pa = upos[ia];
+        it.pb = upos[ib];
+        it.na = (int)bmult[a].size();
+        it.nb = (int)bmult[b].size();
+        it.same = (a == b);
+        int nd = 0;
+        for (int sa = 0; sa < 2; ++sa)
+          for (int sb = 0; sb < 2; ++sb)
+            if (bdom[a][sa] == bdom[b][sb]) {
+              it.ga[nd] = boff[a][sa];
+              it.gb[nd] = boff[b][sb];
+              it.xoff[nd] = bdom[a][sa];   // domain id for now; replaced by the X offset in the layout
+              ++nd;
+            }
+        if (nd == 0) continue;
+        it.ndom = nd;
+        P.aux_items.push_back(it);
+      }
+    }
+    arange[f] = {first, (int64_t)P.aux_items.size() - first};
+  }
+
+  // ------------------------------------------------------------ statistics
+  double fl = 0, fs = 0, fb = 0;
+  for (int f = 0; f < nf; ++f) {
+    const FrontDev &d = P.fronts[f];
+    double n = d.n, s = d.s, R = n - s;
+    fl += 8.0 * (n * n * n - R * R * R) / 6.0;
+    fs += 8.0 * (s * s + 2.0 * s * R);
+    fb += (s * n - s * s / 2.0) * 2.0 * (double)P.elem;
+    if (d.kind == FK_GAMMA) {
+      fl += 8.0 * s * s * s / 3.0;
+      fs += 8.0 * 2.0 * s * s;
+      fb += s * s * 2.0 * (double)P.elem - (s * n - s * s / 2.0) * 2.0 * (double)P.elem;
+    }
+    if (d.kind == FK_AUX) {
+      P.n_front_aux++;
+      P.max_front_aux = std::max(P.max_front_aux, d.n);
+    } else {
+      P.n_front_dom++;
+      P.max_front_dom = std::max(P.max_front_dom, d.n);
+    }
+  }
+  P.flops_factor = fl;
+  P.flops_solve_rhs = fs;
+  P.bytes_factor = fb;
+
+  // ------------------------------------------------------------ numeric layout (T elements)
+  const int64_t mr = P.max_rhs;
+  int64_t at = 0;
+  auto align = [](int64_t x) { return (x + 63) & ~(int64_t)63; };
+  for (int f = 0; f < nf; ++f) {
+    FrontDev &d = P.fronts[f];
+    d.off = at;
+    at = align(at + 2 * (int64_t)d.n * d.n);
+  }
+  for (int f = 0; f < nf; ++f) {
+    FrontDev &d = P.fronts[f];
+    d.woff = at;
+    at = align(at + 2 * (int64_t)d.n * d.wcols);
+  }
+  for (int f = 0; f < nf; ++f) {
+    FrontDev &d = P.fronts[f];
+    if (d.kind != FK_GAMMA) continue;
+    d.xoff = at;
+    at = align(at + 2 * (int64_t)d.s * d.s);
+    d.goff = at;
+    at = align(at + 4 * (int64_t)d.s * mr);
+  }
+  for (int f = 0; f < nf; ++f) {
+    FrontDev &d = P.fronts[f];
+    d.voff = at;
+    at = align(at + 2 * (int64_t)d.n * mr);
+  }
+  P.vf_off = at; at = align(at + 2 * P.n_torn * mr);
+  P.vx_off = at; at = align(at + 2 * P.n_torn * mr);
+  P.vd_off = at; at = align(at + 2 * P.n_mult * mr);
+  P.vl_off = at; at = align(at + 2 * P.n_mult * mr);
+  P.vc_off = at; at = align(at + 2 * P.n_mult * mr);
+  // side arrays
+  int64_t sn = 0;
+  for (int f = 0; f < nf; ++f) {
+    P.fronts[f].soff = sn;
+    sn += P.fronts[f].s;
+  }
+  P.side_n = sn;
+  // aux item X offsets
+  for (auto &it : P.aux_items)
+    for (int t = 0; t < it.ndom; ++t) {
+      int d = (int)it.xoff[t];
+      const FrontDev &g = P.fronts[P.gamma_front[d]];
+      it.xoff[t] = g.xoff;
+      it.g[t] = g.s;
+    }
+  // multiplier references
+  P.mrefs.resize(p.n_mult);
+  for (int64_t m = 0; m < p.n_mult; ++m) {
+    MultRef r;
+    for (int s = 0; s < 2; ++s) {
+      int d = m_dom[2 * m + s];
+      const FrontDev &g = P.fronts[P.gamma_front[d]];
+      r.o[s] = g.goff + gpos_of(d, m_dof[2 * m + s]);
+      r.g[s] = g.s;
+      r.sg[s] = m_sg[2 * m + s];
+      r.row[s] = P.dom_row[d] + m_dof[2 * m + s];
+    }
+    P.mrefs[m] = r;
+  }
+  // interface positions -> multipliers acting on them
+  P.row_gam.assign(P.n_torn, -1);
+  for (int i = 0; i < p.n_dom; ++i) {
+    if (P.gamma[i].empty()) continue;
+    const FrontDev &g = P.fronts[P.gamma_front[i]];
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(P.gamma[i].size());
+    for (int64_t e = p.imap_ptr[i]; e < p.imap_ptr[i + 1]; ++e)
+      lists[gpos_of(i, p.imap_dof[e])].push_back({(int32_t)p.imap_mult[e], p.imap_sign[e]});
+    for (size_t q = 0; q < lists.size(); ++q) {
+      GamRef r;
+      r.o = g.goff + 2 * (int64_t)g.s * mr + (int64_t)q;   // h buffer follows the YG buffer
+      r.g = g.s;
+      r.beg = (int32_t)P.hmult.size();
+      r.cnt = (int32_t)lists[q].size();
+      r.pad = 0;
+      for (auto &pr : lists[q]) {
+        P.hmult.push_back(pr.first);
+        P.hsign.push_back(pr.second);
+      }
+      P.row_gam[P.dom_row[i] + P.gamma[i][q]] = (int32_t)P.grefs.size();
+      P.grefs.push_back(r);
+    }
+  }
+
+  // ------------------------------------------------------------ schedule
+  auto push = [&](std::vector<Launch> &seq, int kind, const std::vector<Item> &its, int p0 = 0, int p1 = 0) {
+    if (its.empty()) return;
+    Launch L;
+    L.kind = kind;
+    L.count = (int32_t)its.size();
+    L.first = (int64_t)P.items.size();
+    L.p0 = p0;
+    L.p1 = p1;
+    P.items.insert(P.items.end(), its.begin(), its.end());
+    seq.push_back(L);
+  };
+  auto factor_steps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
+    int maxt = 0;
+    for (int f : fs) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
+    for (int t = 0; t < maxt; ++t) {
+      std::vector<Item> pan, trs, syr;
+      for (int f : fs) {
+        const FrontDev &d = P.fronts[f];
+        int k = t * NB;
+        if (k >= d.s) continue;
+        int b = std::min(NB, d.s - k);
+        pan.push_back({f, k, 0, 0});
+        int r0 = k + b;
+        int nt = ntiles(d.n - r0, GT);
+        for (int ti = 0; ti < nt; ++ti) trs.push_back({f, k, r0 + ti * GT, 0});
+        for (int ti = 0; ti < nt; ++ti)
+          for (int tj = 0; tj <= ti; ++tj) syr.push_back({f, k, r0 + ti * GT, r0 + tj * GT});
+      }
+      push(seq, L_PANEL, pan);
+      push(seq, L_TRSM, trs);
+      push(seq, L_SYRK, syr);
+    }
+  };
+  auto assemble = [&](std::vector<Launch> &seq, const std::vector<int> &fs, bool aux) {
+    std::vector<Item> as, sc, ag;
+    for (int f : fs) {
+      const FrontDev &d = P.fronts[f];
+      for (int c0 = 0; c0 < d.n; c0 += 64) as.push_back({f, c0, 0, 0});
+      if (!aux) {
+        auto pr = prange[f];
+        for (int64_t b = 0; b < pr.second; b += 4096)
+          sc.push_back({f, (int32_t)(pr.first + b), (int32_t)std::min<int64_t>(4096, pr.second - b), 0});
+      } else {
+        auto ar = arange[f];
+        for (int64_t b = 0; b < ar.second; ++b) ag.push_back({(int32_t)(ar.first + b), 0, 0, 0});
+      }
+    }
+    push(seq, L_ASM, as);
+    push(seq, L_SCAT, sc);
+    push(seq, L_AUXG, ag);
+  };
+  auto by_height = [&](int kind_lo, int kind_hi, bool include_gamma) {
+    std::map<int, std::vector<int>> lv;
+    for (int f = 0; f < nf; ++f) {
+      int k = P.fronts[f].kind;
+      if (k == FK_GAMMA && !include_gamma) continue;
+      if (k < kind_lo || k > kind_hi) continue;
+      lv[F[f].height].push_back(f);
+    }
+    std::vector<std::vector<int>> out;
+    for (auto &kv : lv) out.push_back(kv.second);
+    return out;
+  };
+  std::vector<std::vector<int>> dom_levels = by_height(FK_INTERIOR, FK_INTERIOR, false);
+  std::vector<int> gam;
+  for (int i = 0; i < p.n_dom; ++i)
+    if (P.gamma_front[i] >= 0) gam.push_back(P.gamma_front[i]);
+  // domains without interface: their roots are interior fronts already
+  std::vector<std::vector<int>> aux_levels = by_height(FK_AUX, FK_AUX, false);
+
+  // factor
+  for (auto &lv : dom_levels) {
+    assemble(P.factor_seq, lv, false);
+    factor_steps(P.factor_seq, lv);
+  }
+  if (!gam.empty()) {
+    assemble(P.factor_seq, gam, false);
+    factor_steps(P.factor_seq, gam);
+    int maxt = 0;
+    for (int f : gam) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
+    for (int t = 0; t + 1 < maxt; ++t) {
+      std::vector<Item> pr;
+      for (int f : gam) {
+        const FrontDev &d = P.fronts[f];
+        int T = ntiles(d.s, NB);
+        int kt = T - 2 - t;
+        if (kt < 0) continue;
+        int k = kt * NB;
+        int r0 = k + NB;
+        for (int r = r0; r < d.s; r += GT) pr.push_back({f, k, r, 0});
+      }
+      push(P.factor_seq, L_INVPREP, pr);
+      push(P.factor_seq, L_INVTRMM, pr);
+    }
+    std::vector<Item> sy;
+    for (int f : gam) {
+      const FrontDev &d = P.fronts[f];
+      int nt = ntiles(d.s, GT);
+      for (int ti = 0; ti < nt; ++ti)
+        for (int tj = 0; tj <= ti; ++tj) sy.push_back({f, 0, ti * GT, tj * GT});
+    }
+    push(P.factor_seq, L_INVSYRK, sy);
+  }
+  for (auto &lv : aux_levels) {
+    assemble(P.factor_seq, lv, true);
+    factor_steps(P.factor_seq, lv);
+  }
+
+  // solve: forward over a set of levels
+  int64_t max_part = 0;
+  auto fwd = [&](std::vector<Launch> &seq, const std::vector<std::vector<int>> &levels, bool gamma_only_init) {
+    for (auto &lv : levels) {
+      std::vector<Item> in;
+      for (int f : lv) in.push_back({f, 0, 0, 0});
+      push(seq, S_FINIT, in);
+      if (gamma_only_init) continue;
+      int maxt = 0;
+      for (int f : lv) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
+      for (int t = 0; t < maxt; ++t) {
+        std::vector<Item> dg, up;
+        for (int f : lv) {
+          const FrontDev &d = P.fronts[f];
+          int k = t * NB;
+          if (k >= d.s) continue;
+          int b = std::min(NB, d.s - k);
+          dg.push_back({f, k, 0, 0});
+          for (int r = k + b; r < d.n; r += 256) up.push_back({f, k, r, 0});
+        }
+        push(seq, S_FDIAG, dg);
+        push(seq, S_FUPD, up);
+      }
+      push(seq, S_FFIN, in);
+    }
+  };
+  auto bwd = [&](std::vector<Launch> &seq, const std::vector<std::vector<int>> &levels) {
+    for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
+      auto &lv = *it;
+      std::vector<Item> in;
+      for (int f : lv) in.push_back({f, 0, 0, 0});
+      push(seq, S_BINIT, in);
+      int maxt = 0;
+      for (int f : lv) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
+      for (int t = 0; t < maxt; ++t) {
+        std::vector<Item> pa, dg;
+        int slot = 0;
+        for (int f : lv) {
+          const FrontDev &d = P.fronts[f];
+          int T = ntiles(d.s, NB);
+          int kt = T - 1 - t;
+          if (kt < 0) continue;
+          int k = kt * NB;
+          int b = std::min(NB, d.s - k);
+          int s0 = slot;
+          for (int r = k + b; r < d.n; r += 64) pa.push_back({f, k, r, slot++});
+          dg.push_back({f, k, s0, slot - s0});
+        }
+        max_part = std::max<int64_t>(max_part, slot);
+        push(seq, S_BPART, pa);
+        push(seq, S_BDIAG, dg);
+      }
+      push(seq, S_BFIN, in);
+    }
+  };
+  fwd(P.solve_dom_fwd, dom_levels, false);
+  if (!gam.empty()) fwd(P.solve_dom_fwd, {gam}, true);
+  fwd(P.solve_aux, aux_levels, false);
+  bwd(P.solve_aux, aux_levels);
+  if (!gam.empty()) {
+    std::vector<Item> in;
+    for (int f : gam) in.push_back({f, 0, 0, 0});
+    push(P.solve_dom_bwd, S_BFIN, in);
+  }
+  bwd(P.solve_dom_bwd, dom_levels);
+  for (int f : gam)
+    for (int r = 0; r < P.fronts[f].s; r += 64) P.gemv_items.push_back({f, 0, r, 0});
+  P.max_partials = max_part;
+  P.part_off = at;
+  at = align(at + std::max<int64_t>(1, max_part) * NB * mr * 2);
+  P.t_elems = at;
+
+  // ------------------------------------------------------------ meta blob
+  auto put = [&](const void *src, size_t bytes) -> int64_t {
+    size_t o = (P.meta.size() + 255) & ~(size_t)255;
+    P.meta.resize(o + std::max<size_t>(bytes, 16), 0);
+    if (bytes) std::memcpy(P.meta.data() + o, src, bytes);
+    return (int64_t)o;
+  };
+  P.m_fronts = put(P.fronts.data(), P.fronts.size() * sizeof(FrontDev));
+  P.m_vars = put(P.vars.data(), P.vars.size() * 4);
+  P.m_cfront = put(P.child_front.data(), P.child_front.size() * 4);
+  P.m_crmap = put(P.child_rmap.data(), P.child_rmap.size() * 8);
+  P.m_rmap = put(P.rmap.data(), P.rmap.size() * 4);
+  P.m_spairs = put(P.spairs.data(), P.spairs.size() * sizeof(SPair));
+  P.m_aux = put(P.aux_items.data(), P.aux_items.size() * sizeof(AuxItem));
+  P.m_gpos = put(P.gpos.data(), P.gpos.size() * 4);
+  P.m_gsign = put(P.gsign.data(), P.gsign.size() * 4);
+  P.m_mrefs = put(P.mrefs.data(), P.mrefs.size() * sizeof(MultRef));
+  P.m_grefs = put(P.grefs.data(), P.grefs.size() * sizeof(GamRef));
+  P.m_hmult = put(P.hmult.data(), P.hmult.size() * 4);
+  P.m_hsign = put(P.hsign.data(), P.hsign.size() * 4);
+  P.m_rowgam = put(P.row_gam.data(), P.row_gam.size() * 4);
+  P.m_items = put(P.items.data(), P.items.size() * sizeof(Item));
+  P.m_gemv = put(P.gemv_items.data(), P.gemv_items.size() * sizeof(Item));
+  P.m_csrp = put(P.csr_ptr.data(), P.csr_ptr.size() * 8);
+  P.m_csrc = put(P.csr_col.data(), P.csr_col.size() * 4);
+
+  // ------------------------------------------------------------ workspace (bytes)
+  auto A256 = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
+  int64_t b = 0;
+  P.b_meta = b; b = A256(b + (int64_t)P.meta.size());
+  P.b_num = b; b = A256(b + P.t_elems * (int64_t)P.elem);
+  P.b_side = b; b = A256(b + P.side_n * (16 + 16 + 4 + 4));
+  P.b_vals = b;
+  if (P.precision != 0) b = A256(b + P.nnz_total * 16);
+  P.b_r64 = b;
+  if (P.precision != 0) {
+    int64_t r = 0;
+    P.r_u = r; r += 2 * P.n_torn * mr;
+    P.r_l = r; r += 2 * P.n_mult * mr;
+    P.r_ru = r; r += 2 * P.n_torn * mr;
+    P.r_rl = r; r += 2 * P.n_mult * mr;
+    P.r_nblk = 1024;
+    P.r_part = r; r += 2 * P.r_nblk * mr;   // [blocks x cols] residual / rhs partial sums
+    P.r_norm = r; r += 2 * mr;
+    P.r_fnorm = r; r += mr;
+    b = A256(b + r * 8);
+  }
+  P.b_status = b; b = A256(b + 256);
+  P.b_total = b;
+
+  if (o.verbose) {
+    fprintf(stderr,
+            "[dd] domains %d torn %lld mult %lld | fronts dom %d (max %d) aux %d (max %d) blocks %d\n"
+            "[dd] factor %.3e flop, solve %.3e flop/rhs, factors %.3f GB | workspace %.3f GB | launches factor %zu solve %zu\n",
+            p.n_dom, (long long)P.n_torn, (long long)P.n_mult, P.n_front_dom, P.max_front_dom, P.n_front_aux,
+            P.max_front_aux, nb, P.flops_factor, P.flops_solve_rhs, P.bytes_factor / 1e9, P.b_total / 1e9,
+            P.factor_seq.size(), P.solve_dom_fwd.size() + P.solve_aux.size() + P.solve_dom_bwd.size());
+  }
+  return std::string();
+}
+
+}  // namespace dd
