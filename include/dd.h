@@ -177,6 +177,26 @@ dd_status dd_get_interface_dofs(dd_ctx ctx, int32_t dom, int32_t *count, int32_t
  * FP64 matrix into device memory out (after dd_factor, stream-ordered). */
 dd_status dd_get_interface_inverse(dd_ctx ctx, int32_t dom, dd_z *out, void *hip_stream);
 
+/* Algorithmic factorisation flops of one domain (its fronts and the inverse
+ * of its interface block), from the symbolic structure (host only). */
+dd_status dd_get_domain_flops(dd_ctx ctx, int32_t dom, double *flops);
+
+/* Diagnostics: device timing of one factorisation kernel.  After
+ * dd_kernel_timer_start(ctx, kernel) every launch of that kernel by the
+ * following dd_factor calls is bracketed by a pair of events on its stream
+ * (up to 4096 launches).  dd_kernel_timer_read synchronises and returns the
+ * summed device seconds, the number of launches and their algorithmic flops.
+ * kernel = DD_KERNEL_NONE stops timing. */
+enum {
+    DD_KERNEL_NONE = -1,
+    DD_KERNEL_SCHUR_UPDATE = 0,   /* trailing update A22 -= L21 (L21 D)^T (MFMA)   */
+    DD_KERNEL_PANEL_SOLVE = 1,    /* L21 D = A21 P^T L11^-T, L21 (MFMA)            */
+    DD_KERNEL_PIVOT_TILE = 2,     /* restricted Bunch-Kaufman tile factorisation  */
+    DD_KERNEL_INVERSE_UPDATE = 3  /* interface inverse X = Z^T D^-1 Z (MFMA)      */
+};
+dd_status dd_kernel_timer_start(dd_ctx ctx, int32_t kernel);
+dd_status dd_kernel_timer_read(dd_ctx ctx, double *seconds, int64_t *launches, double *flops);
+
 /* Releases the context (host state only; the workspace stays caller-owned). */
 void dd_destroy(dd_ctx ctx);
 

@@ -48,8 +48,10 @@ class dd_info(C.Structure):
 
 
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
-           "dd_solve", "dd_get_info", "dd_get_interface_dofs", "dd_get_interface_inverse", "dd_destroy",
+           "dd_solve", "dd_get_info", "dd_get_interface_dofs", "dd_get_interface_inverse",
+           "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_destroy",
            "dd_last_error"]
+KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3}
 
 _lib = None
 
@@ -73,6 +75,9 @@ def load():
     lib.dd_get_info.argtypes = [vp, _P(dd_info)]
     lib.dd_get_interface_dofs.argtypes = [vp, C.c_int32, _P(C.c_int32), _P(C.c_int32)]
     lib.dd_get_interface_inverse.argtypes = [vp, C.c_int32, vp, vp]
+    lib.dd_get_domain_flops.argtypes = [vp, C.c_int32, _P(C.c_double)]
+    lib.dd_kernel_timer_start.argtypes = [vp, C.c_int32]
+    lib.dd_kernel_timer_read.argtypes = [vp, _P(C.c_double), _P(C.c_int64), _P(C.c_double)]
     lib.dd_destroy.argtypes = [vp]
     lib.dd_destroy.restype = None
     lib.dd_last_error.argtypes = []
@@ -230,6 +235,19 @@ class Solver:
         out = torch.empty((g, g), dtype=torch.complex128, device=self.device)
         _check(self._lib.dd_get_interface_inverse(self._ctx, dom, C.c_void_p(out.data_ptr()), self._stream(stream)))
         return out.t()      # column-major result
+
+    def domain_flops(self, dom):
+        f = C.c_double()
+        _check(self._lib.dd_get_domain_flops(self._ctx, dom, C.byref(f)))
+        return f.value
+
+    def kernel_timer_start(self, kernel="schur_update"):
+        _check(self._lib.dd_kernel_timer_start(self._ctx, -1 if kernel is None else KERNELS[kernel]))
+
+    def kernel_timer_read(self):
+        t, n, fl = C.c_double(), C.c_int64(), C.c_double()
+        _check(self._lib.dd_kernel_timer_read(self._ctx, C.byref(t), C.byref(n), C.byref(fl)))
+        return {"seconds": t.value, "launches": n.value, "flops": fl.value}
 
     def close(self):
         if getattr(self, "_ctx", None):

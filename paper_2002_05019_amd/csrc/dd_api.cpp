@@ -35,6 +35,8 @@ struct dd_ctx_s {
   double t_setup = 0;
   int refine_iters = 0;
   double rel_resid = 0;
+  dd::KTimer tm;
+  std::vector<hipEvent_t> tev;
 };
 
 #define HIPCHECK(x)                                                                                \
@@ -148,7 +150,7 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
     v = c->ws + c->plan.b_vals;
   }
   HIPCHECK(hipEventRecord(c->ev[0], st));
-  HIPCHECK(dd::factor(c->plan, c->ws, v, st));
+  HIPCHECK(dd::factor(c->plan, c->ws, v, st, c->tm.kind >= 0 ? &c->tm : nullptr));
   HIPCHECK(hipEventRecord(c->ev[1], st));
   c->fact_rec = true;
   c->factored = true;
@@ -284,10 +286,48 @@ dd_status dd_get_interface_inverse(dd_ctx c, int32_t dom, dd_z *out, void *strea
   return DD_OK;
 }
 
+dd_status dd_get_domain_flops(dd_ctx c, int32_t dom, double *flops) {
+  if (!c || !flops) return fail(DD_ERR_ARG, "null argument");
+  if (dom < 0 || dom >= c->plan.n_dom) return fail(DD_ERR_ARG, "domain out of range");
+  *flops = c->plan.dom_flops.empty() ? 0.0 : c->plan.dom_flops[dom];
+  return DD_OK;
+}
+
+dd_status dd_kernel_timer_start(dd_ctx c, int32_t kernel) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  static const int kinds[] = {dd::L_SYRK, dd::L_TRSM, dd::L_PANEL, dd::L_INVSYRK};
+  if (kernel < -1 || kernel > 3) return fail(DD_ERR_ARG, "unknown kernel");
+  if (c->tev.empty() && kernel >= 0) {
+    c->tev.resize(8192);
+    for (auto &e : c->tev) HIPCHECK(hipEventCreate(&e));
+  }
+  c->tm = dd::KTimer();
+  c->tm.kind = kernel < 0 ? -1 : kinds[kernel];
+  c->tm.ev = c->tev.data();
+  c->tm.cap = (int32_t)c->tev.size();
+  return DD_OK;
+}
+
+dd_status dd_kernel_timer_read(dd_ctx c, double *seconds, int64_t *launches, double *flops) {
+  if (!c || !seconds || !launches || !flops) return fail(DD_ERR_ARG, "null argument");
+  double t = 0;
+  for (int i = 0; i + 1 < c->tm.used; i += 2) {
+    float ms = 0;
+    HIPCHECK(hipEventSynchronize(c->tev[i + 1]));
+    HIPCHECK(hipEventElapsedTime(&ms, c->tev[i], c->tev[i + 1]));
+    t += ms * 1e-3;
+  }
+  *seconds = t;
+  *launches = c->tm.launches;
+  *flops = c->tm.flops;
+  return DD_OK;
+}
+
 void dd_destroy(dd_ctx c) {
   if (!c) return;
   if (c->events)
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->ev[i]);
+  for (auto &e : c->tev) (void)hipEventDestroy(e);
   delete c;
 }
 

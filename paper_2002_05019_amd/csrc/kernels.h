@@ -9,11 +9,11 @@
 namespace dd {
 
 // numeric factorisation (enqueue only)
-hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st);
+hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm = nullptr);
 // torn right-hand sides (interleaved complex FP64, ld ldf) -> internal vector
 hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, hipStream_t st);
 // one DD solve of the internal right-hand side (with_c: constraint rhs in vc)
-hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st);
+hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm = nullptr);
 // internal solution / multipliers -> interleaved complex FP64
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
                    hipStream_t st);

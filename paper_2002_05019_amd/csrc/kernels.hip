@@ -1387,9 +1387,17 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
-static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launch> &seq, int nrhs, hipStream_t st) {
+static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launch> &seq, int nrhs, hipStream_t st,
+                          KTimer *tm) {
   for (const Launch &L : seq) {
     dim3 g(L.count), b(256);
+    const bool timed = tm && tm->kind == L.kind && tm->used + 2 <= tm->cap;
+    hipEvent_t *ev = timed ? (hipEvent_t *)tm->ev : nullptr;
+    if (timed) {
+      (void)hipEventRecord(ev[tm->used], st);
+      tm->launches++;
+      tm->flops += L.flops;
+    }
     switch (L.kind) {
       case L_ASM: hipLaunchKernelGGL(k_asm<T>, g, b, 0, st, k, L.first); break;
       case L_SCAT: hipLaunchKernelGGL(k_scat<T>, g, b, 0, st, k, L.first); break;
@@ -1410,41 +1418,45 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case S_BFIN: hipLaunchKernelGGL(k_bfin<T>, g, b, 0, st, k, L.first, nrhs); break;
       default: return hipErrorInvalidValue;
     }
+    if (timed) {
+      (void)hipEventRecord(ev[tm->used + 1], st);
+      tm->used += 2;
+    }
   }
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st) {
+static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm) {
   KP<T> k = make_kp<T>(P, ws, vals);
   hipError_t e = hipMemsetAsync(k.status, 0, 2 * sizeof(int), st);
   if (e != hipSuccess) return e;
-  return run_seq<T>(P, k, P.factor_seq, 0, st);
+  return run_seq<T>(P, k, P.factor_seq, 0, st, tm);
 }
 
 template <typename T>
-static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st) {
+static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm) {
   KP<T> k = make_kp<T>(P, ws, nullptr);
-  hipError_t e = run_seq<T>(P, k, P.solve_dom_fwd, nrhs, st);
+  hipError_t e = run_seq<T>(P, k, P.solve_dom_fwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   if (!P.gemv_items.empty())
     hipLaunchKernelGGL(k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 0, nrhs);
   if (P.n_mult > 0)
     hipLaunchKernelGGL(k_mgather<T>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, nrhs, with_c ? 1 : 0);
-  e = run_seq<T>(P, k, P.solve_aux, nrhs, st);
+  e = run_seq<T>(P, k, P.solve_aux, nrhs, st, tm);
   if (e != hipSuccess) return e;
   if (!P.grefs.empty())
     hipLaunchKernelGGL(k_hgather<T>, dim3(nblk((int64_t)P.grefs.size() * nrhs)), dim3(256), 0, st, k,
                        (int64_t)P.grefs.size(), nrhs);
   if (!P.gemv_items.empty())
     hipLaunchKernelGGL(k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 1, nrhs);
-  e = run_seq<T>(P, k, P.solve_dom_bwd, nrhs, st);
+  e = run_seq<T>(P, k, P.solve_dom_bwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
-hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st) {
-  return P.precision == 0 ? factor_t<double>(P, ws, vals, st) : factor_t<float>(P, ws, vals, st);
+hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm) {
+  return P.precision == 0 ? factor_t<double>(P, ws, vals, st, tm) : factor_t<float>(P, ws, vals, st, tm);
 }
 
 hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, hipStream_t st) {
@@ -1457,9 +1469,9 @@ hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nr
   return hipGetLastError();
 }
 
-hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st) {
-  return P.precision == 0 ? solve_core_t<double>(P, ws, nrhs, with_c, st)
-                          : solve_core_t<float>(P, ws, nrhs, with_c, st);
+hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm) {
+  return P.precision == 0 ? solve_core_t<double>(P, ws, nrhs, with_c, st, tm)
+                          : solve_core_t<float>(P, ws, nrhs, with_c, st, tm);
 }
 
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,

@@ -34,6 +34,17 @@ struct Launch {
   int32_t count;     // number of items / workgroups
   int64_t first;     // first item in the kind's item array
   int32_t p0, p1;    // kind-specific
+  double flops;      // algorithmic real flops of the launch (complex FMA = 8)
+};
+
+// Optional per-kernel event timer (diagnostics): brackets every launch of
+// one kind with a pair of events on the launch stream.
+struct KTimer {
+  int32_t kind = -1;
+  void *ev = nullptr;      // hipEvent_t array
+  int32_t cap = 0, used = 0;
+  int64_t launches = 0;
+  double flops = 0;
 };
 
 struct Plan {
@@ -69,6 +80,7 @@ struct Plan {
   std::vector<Launch> solve_aux;       // aux forward + backward
   std::vector<Launch> solve_dom_bwd;   // Gamma scatter + interior backward
   std::vector<Item> gemv_items;        // interface GEMV items (one per 64-row tile)
+  std::vector<double> dom_flops;       // factor flops per domain (fronts + interface inverse)
   int64_t max_partials = 0;            // partial slots needed by S_BPART (per launch)
 
   // ---- options / layout

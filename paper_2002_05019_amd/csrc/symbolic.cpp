@@ -773,6 +773,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       fs += 8.0 * 2.0 * s * s;
       fb += s * s * 2.0 * (double)P.elem - (s * n - s * s / 2.0) * 2.0 * (double)P.elem;
     }
+    if (d.kind != FK_AUX) {
+      if (P.dom_flops.empty()) P.dom_flops.assign(p.n_dom, 0.0);
+      P.dom_flops[d.dom] += 8.0 * (n * n * n - R * R * R) / 6.0 + (d.kind == FK_GAMMA ? 8.0 * s * s * s / 3.0 : 0.0);
+    }
     if (d.kind == FK_AUX) {
       P.n_front_aux++;
       P.max_front_aux = std::max(P.max_front_aux, d.n);
@@ -871,6 +875,44 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   }
 
   // ------------------------------------------------------------ schedule
+  // algorithmic flops of one work item (complex FMA = 8 real flops)
+  auto item_flops = [&](int kind, const Item &it) -> double {
+    const FrontDev &d = P.fronts[it.f];
+    const int n = d.n;
+    switch (kind) {
+      case L_SYRK: {   // C(r0.., q0..) -= L21 W^T over the lower triangle, K = b
+        const double b = std::min(NB, d.s - it.k);
+        const double rows = std::min(GT, n - it.i), cols = std::min(GT, n - it.j);
+        const double cnt = (it.i == it.j) ? rows * (rows + 1) / 2 : rows * cols;
+        return 8.0 * b * cnt;
+      }
+      case L_TRSM: {   // W = A21 P L^-T (triangular), L21 = W D^-1
+        const double b = std::min(NB, d.s - it.k);
+        const double rows = std::min(GT, n - it.i);
+        return 8.0 * rows * (b * (b + 1) / 2 + b);
+      }
+      case L_PANEL: {
+        const double b = std::min(NB, d.s - it.k);
+        return 8.0 * (b * b * b / 3.0 + b * b * b / 6.0);
+      }
+      case L_INVPREP: {
+        const double rows = std::min(GT, n - it.i);
+        return 8.0 * rows * NB * (NB + 1) / 2;
+      }
+      case L_INVTRMM: {
+        const double rows = std::min(GT, n - it.i);
+        const double kl = std::max(0, std::min(it.i + GT, n) - (it.k + NB));
+        return 8.0 * rows * NB * (kl - rows / 2);
+      }
+      case L_INVSYRK: {
+        const double rows = std::min(GT, n - it.i), cols = std::min(GT, n - it.j);
+        const double cnt = (it.i == it.j) ? rows * (rows + 1) / 2 : rows * cols;
+        return 8.0 * cnt * (n - it.i);
+      }
+      default:
+        return 0.0;
+    }
+  };
   auto push = [&](std::vector<Launch> &seq, int kind, const std::vector<Item> &its, int p0 = 0, int p1 = 0) {
     if (its.empty()) return;
     Launch L;
@@ -879,6 +921,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     L.first = (int64_t)P.items.size();
     L.p0 = p0;
     L.p1 = p1;
+    L.flops = 0;
+    if (kind <= L_INVSYRK)
+      for (const Item &it : its) L.flops += item_flops(kind, it);
     P.items.insert(P.items.end(), its.begin(), its.end());
     seq.push_back(L);
   };
