@@ -3,8 +3,8 @@
 // Every front (dense frontal matrix of the multifrontal LDL^T) is stored
 // column-major, planar complex: the real plane at `off`, the imaginary plane
 // at `off + n*n` (elements of the factor precision T).  Only the lower
-// triangle is meaningful, except in the diagonal NB x NB pivot tiles, whose
-// strict upper triangle holds (L11^-1)^T after the pivot-tile factorisation.
+// triangle is meaningful; after the pivot-tile factorisation the strict lower
+// triangle of every diagonal NB x NB tile holds L11^-1 (not L11).
 #pragma once
 #include <cstdint>
 
@@ -12,6 +12,7 @@ namespace dd {
 
 constexpr int NB = 64;        // pivot-tile width of the blocked LDL^T
 constexpr int GT = 64;        // output tile edge of the MFMA GEMMs
+constexpr int KBLK = 256;     // outer block (columns per trailing update)
 
 enum FrontKind : int32_t { FK_INTERIOR = 0, FK_GAMMA = 1, FK_AUX = 2 };
 

@@ -95,8 +95,12 @@ struct GemmSmem {
 // [kbeg, kend).  fa(m, k, re, im) / fb(c, k, re, im) return operand values
 // (and must leave zeros outside their valid range).  AK / BK select the
 // thread mapping of the loads: true when the operand is contiguous along k.
-// Wave w owns rows 32*(w/2) + [0,32) and columns 32*(w%2) + [0,32) as 2x2
-// MFMA 16x16 blocks (see out_row / out_col for the element positions).
+// The next K chunk is fetched into registers while the current one is
+// multiplied.  Wave w owns rows 32*(w/2) + [0,32) and columns 32*(w%2) +
+// [0,32) as 2x2 MFMA 16x16 blocks.  The MFMA computes the transposed block
+// (first operand from B, second from A) so that the 16 lanes of a result row
+// run along m, the contiguous dimension of the column-major tiles; out_row /
+// out_col give the element positions.
 template <typename T, bool AK, bool BK, class FA, class FB>
 __device__ __forceinline__ void gemm_tile(GemmSmem<T> &sm, int kbeg, int kend, FA fa, FB fb,
                                           typename V4<T>::t (&cr)[2][2], typename V4<T>::t (&ci)[2][2]) {
@@ -108,39 +112,43 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T> &sm, int kbeg, int kend, F
       cr[x][y] = typename V4<T>::t{0, 0, 0, 0};
       ci[x][y] = typename V4<T>::t{0, 0, 0, 0};
     }
+  T ra[2][4], rb[2][4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int rep = 0; rep < 4; ++rep) {
+      const int m = AK ? (tid >> 4) + 16 * rep : (tid & 63);
+      const int k = AK ? (tid & 15) : (tid >> 6) + 4 * rep;
+      T re = 0, im = 0;
+      if (k0 + k < kend) fa(m, k0 + k, re, im);
+      ra[0][rep] = re;
+      ra[1][rep] = im;
+    }
+#pragma unroll
+    for (int rep = 0; rep < 4; ++rep) {
+      const int m = BK ? (tid >> 4) + 16 * rep : (tid & 63);
+      const int k = BK ? (tid & 15) : (tid >> 6) + 4 * rep;
+      T re = 0, im = 0;
+      if (k0 + k < kend) fb(m, k0 + k, re, im);
+      rb[0][rep] = re;
+      rb[1][rep] = im;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
     __syncthreads();
 #pragma unroll
     for (int rep = 0; rep < 4; ++rep) {
-      int m, k;
-      if (AK) {
-        k = tid & 15;
-        m = (tid >> 4) + 16 * rep;
-      } else {
-        m = tid & 63;
-        k = (tid >> 6) + 4 * rep;
-      }
-      T re = 0, im = 0;
-      if (k0 + k < kend) fa(m, k0 + k, re, im);
-      sm.a[0][k][m] = re;
-      sm.a[1][k][m] = im;
-    }
-#pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      int m, k;
-      if (BK) {
-        k = tid & 15;
-        m = (tid >> 4) + 16 * rep;
-      } else {
-        m = tid & 63;
-        k = (tid >> 6) + 4 * rep;
-      }
-      T re = 0, im = 0;
-      if (k0 + k < kend) fb(m, k0 + k, re, im);
-      sm.b[0][k][m] = re;
-      sm.b[1][k][m] = im;
+      const int ma = AK ? (tid >> 4) + 16 * rep : (tid & 63);
+      const int ka = AK ? (tid & 15) : (tid >> 6) + 4 * rep;
+      sm.a[0][ka][ma] = ra[0][rep];
+      sm.a[1][ka][ma] = ra[1][rep];
+      const int mb = BK ? (tid >> 4) + 16 * rep : (tid & 63);
+      const int kb = BK ? (tid & 15) : (tid >> 6) + 4 * rep;
+      sm.b[0][kb][mb] = rb[0][rep];
+      sm.b[1][kb][mb] = rb[1][rep];
     }
     __syncthreads();
+    if (k0 + TK < kend) fetch(k0 + TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -156,26 +164,28 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T> &sm, int kbeg, int kend, F
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          cr[x][y] = mfma16(ar[x], br[y], cr[x][y]);
-          cr[x][y] = mfma16(-ai[x], bi[y], cr[x][y]);
-          ci[x][y] = mfma16(ar[x], bi[y], ci[x][y]);
-          ci[x][y] = mfma16(ai[x], br[y], ci[x][y]);
+          cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
+          cr[x][y] = mfma16(-bi[y], ai[x], cr[x][y]);
+          ci[x][y] = mfma16(bi[y], ar[x], ci[x][y]);
+          ci[x][y] = mfma16(br[y], ai[x], ci[x][y]);
         }
     }
   }
 }
 
-// Result element i of a 16x16 block sits at row 4*(lane/16) + i for the FP32
-// instruction and at row lane/16 + 4*i for the FP64 one (column lane%16 both).
-template <typename T>
-__device__ __forceinline__ int out_row(int x, int i) {
+// Position of element i of result block (x, y): row (the m index) and
+// column (the c index) inside the GT x GT tile.  The MFMA result row index is
+// 4*(lane/16) + i for the FP32 instruction and lane/16 + 4*i for the FP64 one;
+// its column is lane%16.
+__device__ __forceinline__ int out_row(int x) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (sizeof(T) == 8) return (w >> 1) * 32 + x * 16 + (lane >> 4) + 4 * i;
-  return (w >> 1) * 32 + x * 16 + (lane >> 4) * 4 + i;
+  return (w >> 1) * 32 + x * 16 + (lane & 15);
 }
-__device__ __forceinline__ int out_col(int y) {
+template <typename T>
+__device__ __forceinline__ int out_col(int y, int i) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  return (w & 1) * 32 + y * 16 + (lane & 15);
+  if (sizeof(T) == 8) return (w & 1) * 32 + y * 16 + (lane >> 4) + 4 * i;
+  return (w & 1) * 32 + y * 16 + (lane >> 4) * 4 + i;
 }
 
 __device__ __forceinline__ double cabs1(double r, double i) { return fabs(r) + fabs(i); }
@@ -515,12 +525,12 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = out_row<T>(x, i), c = out_col(y);
+        const int m = out_row(x), c = out_col<T>(y, i);
         wr[m][c] = cr[x][y][i];
         wi[m][c] = ci[x][y][i];
         if (r0 + m < n && c < b) {
-          Wr[(r0 + m) + (int64_t)c * n] = cr[x][y][i];
-          Wi[(r0 + m) + (int64_t)c * n] = ci[x][y][i];
+          Wr[(r0 + m) + (int64_t)(it.j + c) * n] = cr[x][y][i];
+          Wi[(r0 + m) + (int64_t)(it.j + c) * n] = ci[x][y][i];
         }
       }
   __syncthreads();
@@ -543,13 +553,21 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
   }
 }
 
-// trailing update: C(r0.., q0..) -= L21 W^T
+// Update of the trailing part by the factored columns [k, kend) of the current
+// outer block: C(r0.., q0..) -= L21(r0.., k..kend) W(q0.., 0..kend-k)^T.
+// Trailing update (q0 >= block end): lower tiles of the trailing matrix,
+// kend = min(k + KBLK, s).  Column update (q0 < block end): the pivot tile
+// column starting at q0 receives the block's earlier tiles, kend = q0.
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int k = it.k, r0 = it.i, q0 = it.j, n = f.n, b = min(NB, f.s - k);
+  const int k = it.k, r0 = it.i, q0 = it.j, n = f.n;
+  const int bend = min(k + KBLK, f.s);
+  const bool colupd = q0 < bend;
+  const int kend = colupd ? q0 : bend;
+  const int qend = colupd ? min(q0 + NB, f.s) : n;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
   const T *Wr = p.num + f.woff;
@@ -557,21 +575,21 @@ __global__ __launch_bounds__(256) void k_syrk(KP<T> p, int64_t first) {
   auto fa = [&](int m, int kk, T &re, T &im) {
     const int r = r0 + m;
     if (r < n) {
-      const int64_t o = r + (int64_t)(k + kk) * n;
+      const int64_t o = r + (int64_t)kk * n;
       re = fr[o];
       im = fi[o];
     }
   };
   auto fb = [&](int c, int kk, T &re, T &im) {
     const int q = q0 + c;
-    if (q < n) {
-      const int64_t o = q + (int64_t)kk * n;
+    if (q < qend) {
+      const int64_t o = q + (int64_t)(kk - k) * n;
       re = Wr[o];
       im = Wi[o];
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, false>(sm, 0, b, fa, fb, cr, ci);
+  gemm_tile<T, false, false>(sm, k, kend, fa, fb, cr, ci);
   const bool diag = (r0 == q0);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -579,9 +597,9 @@ __global__ __launch_bounds__(256) void k_syrk(KP<T> p, int64_t first) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = out_row<T>(x, i), c = out_col(y);
+        const int m = out_row(x), c = out_col<T>(y, i);
         const int r = r0 + m, q = q0 + c;
-        if (r < n && q < n && (!diag || m >= c)) {
+        if (r < n && q < qend && (!diag || m >= c)) {
           const int64_t o = r + (int64_t)q * n;
           fr[o] -= cr[x][y][i];
           fi[o] -= ci[x][y][i];
@@ -638,7 +656,7 @@ __global__ __launch_bounds__(256) void k_invprep(KP<T> p, int64_t first) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = out_row<T>(x, i), c = out_col(y);
+        const int m = out_row(x), c = out_col<T>(y, i);
         if (r0 + m < n) {
           Wr[(r0 + m) + (int64_t)c * n] = cr[x][y][i];
           Wi[(r0 + m) + (int64_t)c * n] = ci[x][y][i];
@@ -674,7 +692,7 @@ __global__ __launch_bounds__(256) void k_invtrmm(KP<T> p, int64_t first) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = out_row<T>(x, i), c = out_col(y);
+        const int m = out_row(x), c = out_col<T>(y, i);
         if (r0 + m < n) {
           const int64_t o = (r0 + m) + (int64_t)(k + c) * n;
           fr[o] = -cr[x][y][i];
@@ -730,7 +748,7 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = out_row<T>(x, i), c = out_col(y);
+        const int m = out_row(x), c = out_col<T>(y, i);
         const int a = a0 + m, cc = c0 + c;
         if (a < n && cc < n && (!diag || m >= c)) {
           const int pa = (a / NB) * NB + pm[a], pc = (cc / NB) * NB + pm[cc];

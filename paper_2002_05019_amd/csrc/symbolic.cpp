@@ -605,7 +605,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       for (int v : h.rows) P.vars.push_back(v);
       d.vbase = P.dom_row[h.dom];
     }
-    d.wcols = h.kind == FK_GAMMA ? 2 * NB : NB;
+    d.wcols = std::max(KBLK, h.kind == FK_GAMMA ? 2 * NB : NB);
   }
   // children + reverse extend-add maps
   {
@@ -880,11 +880,16 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     const FrontDev &d = P.fronts[it.f];
     const int n = d.n;
     switch (kind) {
-      case L_SYRK: {   // C(r0.., q0..) -= L21 W^T over the lower triangle, K = b
-        const double b = std::min(NB, d.s - it.k);
-        const double rows = std::min(GT, n - it.i), cols = std::min(GT, n - it.j);
+      case L_SYRK: {   // C(r0.., q0..) -= L21 W^T over the lower triangle
+        // item: k = first column of the outer block; j = q0.  K length:
+        // trailing update (i >= block end): block width; column update: q0 - k
+        const int kend = std::min(it.k + KBLK, d.s);
+        const bool colupd = it.j < kend;
+        const double K = colupd ? (it.j - it.k) : (kend - it.k);
+        const double rows = std::min(GT, n - it.i);
+        const double cols = colupd ? std::min(NB, d.s - it.j) : std::min(GT, n - it.j);
         const double cnt = (it.i == it.j) ? rows * (rows + 1) / 2 : rows * cols;
-        return 8.0 * b * cnt;
+        return 8.0 * K * cnt;
       }
       case L_TRSM: {   // W = A21 P L^-T (triangular), L21 = W D^-1
         const double b = std::min(NB, d.s - it.k);
@@ -924,28 +929,58 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     L.flops = 0;
     if (kind <= L_INVSYRK)
       for (const Item &it : its) L.flops += item_flops(kind, it);
-    P.items.insert(P.items.end(), its.begin(), its.end());
+    const bool gemm = kind == L_SYRK || kind == L_TRSM || kind == L_INVPREP || kind == L_INVTRMM || kind == L_INVSYRK;
+    if (gemm && its.size() >= 16) {
+      // Workgroup b runs on XCD b % 8: give each XCD a contiguous run of the
+      // item list (items sharing an operand panel are adjacent), so that
+      // panel is read into one L2.
+      const int64_t N = (int64_t)its.size();
+      int64_t start[8], at = 0;
+      for (int x = 0; x < 8; ++x) {
+        start[x] = at;
+        at += (N - x + 7) / 8;
+      }
+      for (int64_t b = 0; b < N; ++b) P.items.push_back(its[start[b % 8] + b / 8]);
+    } else {
+      P.items.insert(P.items.end(), its.begin(), its.end());
+    }
     seq.push_back(L);
   };
+  // Blocked right-looking LDL^T with outer blocks of KBLK columns: inside a
+  // block every pivot tile first receives the updates of the block's earlier
+  // tiles (column update), is factored (pivot tile + panel solve), and after
+  // the block one trailing update with K = KBLK is applied.
   auto factor_steps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
     int maxt = 0;
     for (int f : fs) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
-    for (int t = 0; t < maxt; ++t) {
-      std::vector<Item> pan, trs, syr;
+    const int G = KBLK / NB;
+    for (int ob = 0; ob < maxt; ob += G) {
+      for (int t = ob; t < ob + G && t < maxt; ++t) {
+        std::vector<Item> upd, pan, trs;
+        for (int f : fs) {
+          const FrontDev &d = P.fronts[f];
+          const int k = t * NB, o = ob * NB;
+          if (k >= d.s) continue;
+          const int b = std::min(NB, d.s - k);
+          if (t > ob)
+            for (int r0 = k; r0 < d.n; r0 += GT) upd.push_back({f, o, r0, k});
+          pan.push_back({f, k, 0, 0});
+          for (int r0 = k + b; r0 < d.n; r0 += GT) trs.push_back({f, k, r0, k - o});
+        }
+        push(seq, L_SYRK, upd);
+        push(seq, L_PANEL, pan);
+        push(seq, L_TRSM, trs);
+      }
+      std::vector<Item> syr;
       for (int f : fs) {
         const FrontDev &d = P.fronts[f];
-        int k = t * NB;
-        if (k >= d.s) continue;
-        int b = std::min(NB, d.s - k);
-        pan.push_back({f, k, 0, 0});
-        int r0 = k + b;
-        int nt = ntiles(d.n - r0, GT);
-        for (int ti = 0; ti < nt; ++ti) trs.push_back({f, k, r0 + ti * GT, 0});
+        const int o = ob * NB;
+        if (o >= d.s) continue;
+        const int kend = std::min(o + KBLK, d.s);
+        const int nt = ntiles(d.n - kend, GT);
         for (int ti = 0; ti < nt; ++ti)
-          for (int tj = 0; tj <= ti; ++tj) syr.push_back({f, k, r0 + ti * GT, r0 + tj * GT});
+          for (int tj = 0; tj <= ti; ++tj) syr.push_back({f, o, kend + ti * GT, kend + tj * GT});
       }
-      push(seq, L_PANEL, pan);
-      push(seq, L_TRSM, trs);
       push(seq, L_SYRK, syr);
     }
   };
