@@ -100,7 +100,10 @@ typedef struct {
                               sized for it, larger nrhs are solved in blocks
                               (default 64)                                       */
     int32_t leaf_size;     /* nested-dissection leaf size (default 48)          */
-    int32_t use_graph;     /* reserved, must be 0                               */
+    int32_t use_graph;     /* 1: capture the factorisation (per value pointer)
+                              and the solve core (per column count) into
+                              hipGraphs on first use and replay them; 0: plain
+                              launches.  Timed kernels always run plain.       */
     int32_t verbose;       /* print the symbolic summary to stderr              */
 } dd_options;
 

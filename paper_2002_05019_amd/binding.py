@@ -115,7 +115,7 @@ class Solver:
 
     def __init__(self, rowptr, colind, n_mult, imap_ptr, imap_dof, imap_mult, imap_sign, xyz=None,
                  precision="fp64", max_rhs=64, leaf_size=48, refine_tol=1e-9, refine_maxit=20,
-                 verbose=False):
+                 use_graph=False, verbose=False):
         lib = load()
         self._lib = lib
         nd = len(rowptr)
@@ -147,6 +147,7 @@ class Solver:
         opt.refine_tol = float(refine_tol)
         opt.refine_maxit = int(refine_maxit)
         opt.verbose = int(bool(verbose))
+        opt.use_graph = int(bool(use_graph))
         self.precision = precision
         self.max_rhs = int(max_rhs)
         ctx = C.c_void_p()

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <chrono>
+#include <map>
+#include <utility>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -37,7 +39,51 @@ struct dd_ctx_s {
   double rel_resid = 0;
   dd::KTimer tm;
   std::vector<hipEvent_t> tev;
+  // hipGraph replay: captured on an internal stream, launched on the caller's
+  hipStream_t cap = nullptr;
+  std::map<const void *, hipGraphExec_t> gfactor;
+  std::map<std::pair<int, int>, hipGraphExec_t> gsolve;
 };
+
+namespace {
+void drop_graphs(dd_ctx_s *c) {
+  for (auto &kv : c->gfactor) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : c->gsolve) (void)hipGraphExecDestroy(kv.second);
+  c->gfactor.clear();
+  c->gsolve.clear();
+}
+
+// Records `enqueue` (launches only) on the capture stream into an executable graph.
+template <class F>
+hipError_t capture(dd_ctx_s *c, F enqueue, hipGraphExec_t *out) {
+  hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e1 = enqueue(c->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap, &g);
+  if (e1 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return e1;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+hipError_t run_solve_core(dd_ctx_s *c, int nrhs, bool with_c, hipStream_t st) {
+  if (!c->opt.use_graph) return dd::solve_core(c->plan, c->ws, nrhs, with_c, st);
+  auto key = std::make_pair(nrhs, with_c ? 1 : 0);
+  auto it = c->gsolve.find(key);
+  if (it == c->gsolve.end()) {
+    hipGraphExec_t ge;
+    hipError_t e = capture(c, [&](hipStream_t s) { return dd::solve_core(c->plan, c->ws, nrhs, with_c, s); }, &ge);
+    if (e != hipSuccess) return e;
+    it = c->gsolve.emplace(key, ge).first;
+  }
+  return hipGraphLaunch(it->second, st);
+}
+}  // namespace
 
 #define HIPCHECK(x)                                                                                \
   do {                                                                                             \
@@ -74,7 +120,7 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
     if (o.leaf_size < 1) return fail(DD_ERR_ARG, "leaf_size must be >= 1");
     if (o.refine_maxit < 0) return fail(DD_ERR_ARG, "refine_maxit must be >= 0");
     if (!(o.refine_tol > 0)) return fail(DD_ERR_ARG, "refine_tol must be > 0");
-    if (o.use_graph != 0) return fail(DD_ERR_ARG, "use_graph is reserved and must be 0");
+    if (o.use_graph != 0 && o.use_graph != 1) return fail(DD_ERR_ARG, "use_graph must be 0 or 1");
     if (prob->n_dom < 1 || !prob->dom) return fail(DD_ERR_ARG, "need at least one domain");
     auto t0 = std::chrono::steady_clock::now();
     dd::ProblemView pv;
@@ -132,6 +178,8 @@ dd_status dd_bind_workspace(dd_ctx c, void *dev, int64_t bytes) {
     for (int i = 0; i < 4; ++i) HIPCHECK(hipEventCreate(&c->ev[i]));
     c->events = true;
   }
+  if (!c->cap) HIPCHECK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  drop_graphs(c);
   c->ws = (uint8_t *)dev;
   c->ws_bytes = bytes;
   c->factored = false;
@@ -150,7 +198,17 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
     v = c->ws + c->plan.b_vals;
   }
   HIPCHECK(hipEventRecord(c->ev[0], st));
-  HIPCHECK(dd::factor(c->plan, c->ws, v, st, c->tm.kind >= 0 ? &c->tm : nullptr));
+  if (c->opt.use_graph && c->tm.kind < 0) {
+    auto it = c->gfactor.find(v);
+    if (it == c->gfactor.end()) {
+      hipGraphExec_t ge;
+      HIPCHECK(capture(c, [&](hipStream_t s) { return dd::factor(c->plan, c->ws, v, s, nullptr); }, &ge));
+      it = c->gfactor.emplace(v, ge).first;
+    }
+    HIPCHECK(hipGraphLaunch(it->second, st));
+  } else {
+    HIPCHECK(dd::factor(c->plan, c->ws, v, st, c->tm.kind >= 0 ? &c->tm : nullptr));
+  }
   HIPCHECK(hipEventRecord(c->ev[1], st));
   c->fact_rec = true;
   c->factored = true;
@@ -181,7 +239,7 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
     dd_z *uj = u + (int64_t)j0 * ldu;
     dd_z *lj = lam ? lam + (int64_t)j0 * ldl : nullptr;
     HIPCHECK(dd::rhs_in(P, c->ws, fj, ldf, nb, st));
-    HIPCHECK(dd::solve_core(P, c->ws, nb, false, st));
+    HIPCHECK(run_solve_core(c, nb, false, st));
     if (P.precision == 0) {
       HIPCHECK(dd::sol_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
       continue;
@@ -216,7 +274,7 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
         g_err = "refinement did not reach refine_tol";
         break;
       }
-      HIPCHECK(dd::solve_core(P, c->ws, nb, true, st));
+      HIPCHECK(run_solve_core(c, nb, true, st));
       HIPCHECK(dd::refine_update(P, c->ws, nb, st));
       ++it;
     }
@@ -328,6 +386,8 @@ void dd_destroy(dd_ctx c) {
   if (c->events)
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->ev[i]);
   for (auto &e : c->tev) (void)hipEventDestroy(e);
+  drop_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
 

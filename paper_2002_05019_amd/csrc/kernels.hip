@@ -191,31 +191,63 @@ __device__ __forceinline__ int out_col(int y, int i) {
 __device__ __forceinline__ double cabs1(double r, double i) { return fabs(r) + fabs(i); }
 
 // ---------------------------------------------------------------------------
-// assembly
+// assembly: pull extend-add.  Workgroup item (f, c0, r0) assigns the
+// lower-triangle entries of rows [r0, r0+256) x columns [c0, c0+64) of front
+// f: the sum of the children's update-block entries mapped there (zero where
+// no child contributes).  Children are taken in groups of 8; a thread keeps
+// the children's row-map entries of its row in registers, the column maps of
+// the block sit in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_asm(KP<T> p, int64_t first) {
+  __shared__ int rmc[8][64];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n;
+  const int n = f.n, c0 = it.k, r = it.i + threadIdx.x;
+  const int cend = min(c0 + 64, n);
   T *re = p.num + f.off;
   T *im = re + (int64_t)n * n;
-  const int cend = min(it.k + 64, n);
-  for (int c = it.k; c < cend; ++c) {
-    for (int r = c + threadIdx.x; r < n; r += 256) {
-      T vr = 0, vi = 0;
-      for (int ch = 0; ch < f.nchild; ++ch) {
-        const int32_t *rm = p.rmap + p.crmap[f.child + ch];
-        const int rc = rm[c];
-        if (rc < 0) continue;
-        const int rr = rm[r];
-        if (rr < 0) continue;
-        const FrontDev &cf = p.F[p.cfront[f.child + ch]];
-        const int64_t o = cf.off + (cf.s + rr) + (int64_t)(cf.s + rc) * cf.n;
-        vr += p.num[o];
-        vi += p.num[o + (int64_t)cf.n * cf.n];
+  for (int g0 = 0; g0 < max(f.nchild, 1); g0 += 8) {
+    const int ng = min(8, f.nchild - g0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 8 * 64; e += 256) {
+      const int ch = e / 64, c = c0 + (e % 64);
+      rmc[ch][e % 64] = (ch < ng && c < n) ? p.rmap[p.crmap[f.child + g0 + ch] + c] : -1;
+    }
+    __syncthreads();
+    if (r >= n) continue;
+    int rr[8];
+    int64_t coff[8], cn[8], cplane[8];
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      rr[ch] = -1;
+      coff[ch] = cn[ch] = cplane[ch] = 0;
+      if (ch < ng) {
+        rr[ch] = p.rmap[p.crmap[f.child + g0 + ch] + r];
+        const FrontDev &cf = p.F[p.cfront[f.child + g0 + ch]];
+        cn[ch] = cf.n;
+        cplane[ch] = (int64_t)cf.n * cf.n;
+        coff[ch] = cf.off + cf.s + (int64_t)cf.s * cf.n;   // origin of the update block
       }
-      re[r + (int64_t)c * n] = vr;
-      im[r + (int64_t)c * n] = vi;
+    }
+    for (int c = c0; c < cend && c <= r; ++c) {
+      T vr = 0, vi = 0;
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        const int rc = rmc[ch][c - c0];
+        if (rr[ch] >= 0 && rc >= 0) {
+          const int64_t o = coff[ch] + rr[ch] + rc * cn[ch];
+          vr += p.num[o];
+          vi += p.num[o + cplane[ch]];
+        }
+      }
+      const int64_t o = r + (int64_t)c * n;
+      if (g0 == 0) {
+        re[o] = vr;
+        im[o] = vi;
+      } else {
+        re[o] += vr;
+        im[o] += vi;
+      }
     }
   }
 }
@@ -624,32 +656,34 @@ __device__ __forceinline__ void zval(const T *fr, const T *fi, int n, int r, int
   }
 }
 
-// W' = P L_stored(rows r0.., tile k) L_kk^-1
+// Recursive inverse of the fully-summed block: for a tile range split at m0
+// whose two halves already hold Z, with L_true = P L_stored (lazy tile perms):
+//   T1  = L_true(second half rows, first half cols) Z11   -> upper triangle (transposed)
+//   Z21 = -Z22 T1                                         -> lower triangle
+// Item (f, m0, r0, c0): output tile rows [r0, r0+64), columns [c0, c0+64).
 template <typename T>
-__global__ __launch_bounds__(256) void k_invprep(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256) void k_zrec1(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int k = it.k, r0 = it.i, n = f.n;
+  const int m0 = it.k, r0 = it.i, c0 = it.j, n = f.n, s = f.s;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
   const int32_t *pm = p.perm + f.soff;
   auto fa = [&](int m, int kk, T &re, T &im) {
     const int r = r0 + m;
-    if (r < n) {
+    if (r < s) {
       const int rs = (r / NB) * NB + pm[r];
-      const int64_t o = rs + (int64_t)(k + kk) * n;
+      const int64_t o = rs + (int64_t)kk * n;
       re = fr[o];
       im = fi[o];
     }
   };
-  auto fb = [&](int c, int kk, T &re, T &im) {   // Y(kk, c), Y = L_kk^-1
-    zval(fr, fi, n, k + kk, k + c, re, im);
+  auto fb = [&](int c, int kk, T &re, T &im) {   // Z(kk, c0 + c)
+    zval(fr, fi, n, kk, c0 + c, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, true>(sm, 0, NB, fa, fb, cr, ci);
-  T *Wr = p.num + f.woff;
-  T *Wi = Wr + (int64_t)n * f.wcols;
+  gemm_tile<T, false, true>(sm, c0, m0, fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -657,35 +691,35 @@ __global__ __launch_bounds__(256) void k_invprep(KP<T> p, int64_t first) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = out_row(x), c = out_col<T>(y, i);
-        if (r0 + m < n) {
-          Wr[(r0 + m) + (int64_t)c * n] = cr[x][y][i];
-          Wi[(r0 + m) + (int64_t)c * n] = ci[x][y][i];
+        if (r0 + m < s && c0 + c < m0) {
+          const int64_t o = (c0 + c) + (int64_t)(r0 + m) * n;
+          fr[o] = cr[x][y][i];
+          fi[o] = ci[x][y][i];
         }
       }
 }
 
-// Z(r0.., tile k) = -Z22 W'
 template <typename T>
-__global__ __launch_bounds__(256) void k_invtrmm(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256) void k_zrec2(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int k = it.k, r0 = it.i, n = f.n;
+  const int m0 = it.k, r0 = it.i, c0 = it.j, n = f.n, s = f.s;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
-  const T *Wr = p.num + f.woff;
-  const T *Wi = Wr + (int64_t)n * f.wcols;
-  auto fa = [&](int m, int kk, T &re, T &im) {
+  auto fa = [&](int m, int kk, T &re, T &im) {   // Z(r0 + m, kk)
     const int r = r0 + m;
-    if (r < n) zval(fr, fi, n, r, kk, re, im);
+    if (r < s) zval(fr, fi, n, r, kk, re, im);
   };
-  auto fb = [&](int c, int kk, T &re, T &im) {
-    const int64_t o = kk + (int64_t)c * n;
-    re = Wr[o];
-    im = Wi[o];
+  auto fb = [&](int c, int kk, T &re, T &im) {   // T1(kk, c0 + c), stored at (c0 + c, kk)
+    if (c0 + c < m0) {
+      const int64_t o = (c0 + c) + (int64_t)kk * n;
+      re = fr[o];
+      im = fi[o];
+    }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, true>(sm, k + NB, min(r0 + GT, n), fa, fb, cr, ci);
+  gemm_tile<T, false, false>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -693,8 +727,8 @@ __global__ __launch_bounds__(256) void k_invtrmm(KP<T> p, int64_t first) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = out_row(x), c = out_col<T>(y, i);
-        if (r0 + m < n) {
-          const int64_t o = (r0 + m) + (int64_t)(k + c) * n;
+        if (r0 + m < s && c0 + c < m0) {
+          const int64_t o = (r0 + m) + (int64_t)(c0 + c) * n;
           fr[o] = -cr[x][y][i];
           fi[o] = -ci[x][y][i];
         }
@@ -795,10 +829,117 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
   }
 }
 
-// y_k = L_kk^-1 P_k v_k
+// Loads the strict lower triangle of the diagonal tile (L_kk^-1) into LDS.
+template <typename T>
+__device__ __forceinline__ void load_ytile(T (&yr)[NB][NB + 1], T (&yi)[NB][NB + 1], const T *fr, const T *fi,
+                                           int n, int k, int b) {
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int a = e % NB, c = e / NB;
+    T vr = 0, vi = 0;
+    if (a < b && c < a) {
+      const int64_t o = (k + a) + (int64_t)(k + c) * n;
+      vr = fr[o];
+      vi = fi[o];
+    }
+    yr[a][c] = vr;
+    yi[a][c] = vi;
+  }
+}
+
+// y_k = L_kk^-1 P_k v_k for columns [j0, j0+nj) of the front vector v (ld n);
+// y is also left in (sr, si).
+template <typename T>
+__device__ __forceinline__ void tile_forward(T (&sr)[NB][65], T (&si)[NB][65], const T (&yr)[NB][NB + 1],
+                                             const T (&yi)[NB][NB + 1], T *vr, T *vi, int n, int k, int b,
+                                             const int32_t *pm, int j0, int nj) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < b * nj; e += 256) {
+    const int a = e % b, j = e / b;
+    const int64_t o = k + pm[a] + (int64_t)(j0 + j) * n;
+    sr[a][j] = vr[o];
+    si[a][j] = vi[o];
+  }
+  __syncthreads();
+  T ur[16], ui[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    ur[q] = ui[q] = 0;
+    if (e < b * nj) {
+      const int a = e % b, j = e / b;
+      T xr = sr[a][j], xi = si[a][j];
+      for (int c = 0; c < a; ++c) {
+        const T lr = yr[a][c], li = yi[a][c];
+        xr += lr * sr[c][j] - li * si[c][j];
+        xi += lr * si[c][j] + li * sr[c][j];
+      }
+      ur[q] = xr;
+      ui[q] = xi;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    if (e < b * nj) {
+      const int a = e % b, j = e / b;
+      sr[a][j] = ur[q];
+      si[a][j] = ui[q];
+      vr[k + a + (int64_t)(j0 + j) * n] = ur[q];
+      vi[k + a + (int64_t)(j0 + j) * n] = ui[q];
+    }
+  }
+  __syncthreads();
+}
+
+// v(r, j0..j0+nj) -= L(r, k..k+b) y for one row r (y in sr/si)
+template <typename T>
+__device__ __forceinline__ void row_update(const T (&sr)[NB][65], const T (&si)[NB][65], const T *fr, const T *fi,
+                                           T *vr, T *vi, int n, int k, int b, int r, int j0, int nj) {
+  for (int jj = 0; jj < nj; jj += 8) {
+    T ar[8], ai[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
+    int c = 0;
+    for (; c + 4 <= b; c += 4) {
+      T lr[4], li[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t o = r + (int64_t)(k + c + u) * n;
+        lr[u] = fr[o];
+        li[u] = fi[o];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          ar[q] += lr[u] * sr[c + u][jj + q] - li[u] * si[c + u][jj + q];
+          ai[q] += lr[u] * si[c + u][jj + q] + li[u] * sr[c + u][jj + q];
+        }
+    }
+    for (; c < b; ++c) {
+      const int64_t o = r + (int64_t)(k + c) * n;
+      const T lr = fr[o], li = fi[o];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        ar[q] += lr * sr[c][jj + q] - li * si[c][jj + q];
+        ai[q] += lr * si[c][jj + q] + li * sr[c][jj + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (jj + q < nj) {
+        const int64_t o = r + (int64_t)(j0 + jj + q) * n;
+        vr[o] -= ar[q];
+        vi[o] -= ai[q];
+      }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fdiag(KP<T> p, int64_t first, int nrhs) {
   __shared__ T sr[NB][65], si[NB][65];
+  __shared__ T yr[NB][NB + 1], yi[NB][NB + 1];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int n = f.n, k = it.k, b = min(NB, f.s - k);
@@ -807,37 +948,17 @@ __global__ __launch_bounds__(256) void k_fdiag(KP<T> p, int64_t first, int nrhs)
   T *vi = vr + (int64_t)n * mr;
   const T *fr = p.num + f.off;
   const T *fi = fr + (int64_t)n * n;
-  const int32_t *pm = p.perm + f.soff + k;
+  load_ytile(yr, yi, fr, fi, n, k, b);
   for (int j0 = 0; j0 < nrhs; j0 += 64) {
     const int nj = min(64, nrhs - j0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * nj; e += 256) {
-      const int a = e % b, j = e / b;
-      const int64_t o = k + pm[a] + (int64_t)(j0 + j) * n;
-      sr[a][j] = vr[o];
-      si[a][j] = vi[o];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * nj; e += 256) {
-      const int a = e % b, j = e / b;
-      T yr = sr[a][j], yi = si[a][j];
-      for (int c = 0; c < a; ++c) {
-        const int64_t o = (k + a) + (int64_t)(k + c) * n;
-        const T lr = fr[o], li = fi[o];
-        yr += lr * sr[c][j] - li * si[c][j];
-        yi += lr * si[c][j] + li * sr[c][j];
-      }
-      const int64_t o = k + a + (int64_t)(j0 + j) * n;
-      vr[o] = yr;
-      vi[o] = yi;
-    }
+    tile_forward(sr, si, yr, yi, vr, vi, n, k, b, p.perm + f.soff + k, j0, nj);
   }
 }
 
 // v(rows r0..r0+255, r >= k+b) -= L21(:, tile k) y_k
 template <typename T>
 __global__ __launch_bounds__(256) void k_fupd(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T yr[NB][65], yi[NB][65];
+  __shared__ T sr[NB][65], si[NB][65];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int n = f.n, k = it.k, b = min(NB, f.s - k);
@@ -853,65 +974,25 @@ __global__ __launch_bounds__(256) void k_fupd(KP<T> p, int64_t first, int nrhs) 
     for (int e = threadIdx.x; e < b * nj; e += 256) {
       const int a = e % b, j = e / b;
       const int64_t o = k + a + (int64_t)(j0 + j) * n;
-      yr[a][j] = vr[o];
-      yi[a][j] = vi[o];
+      sr[a][j] = vr[o];
+      si[a][j] = vi[o];
     }
     __syncthreads();
-    if (r < n) {
-      for (int jj = 0; jj < nj; jj += 8) {
-        T ar[8], ai[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
-        for (int c = 0; c < b; ++c) {
-          const int64_t o = r + (int64_t)(k + c) * n;
-          const T lr = fr[o], li = fi[o];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            ar[q] += lr * yr[c][jj + q] - li * yi[c][jj + q];
-            ai[q] += lr * yi[c][jj + q] + li * yr[c][jj + q];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (jj + q < nj) {
-            const int64_t o = r + (int64_t)(j0 + jj + q) * n;
-            vr[o] -= ar[q];
-            vi[o] -= ai[q];
-          }
-      }
-    }
+    if (r < n) row_update(sr, si, fr, fi, vr, vi, n, k, b, r, j0, nj);
   }
 }
+
+template <typename T>
+__device__ __forceinline__ void apply_dinv(const KP<T> &p, const FrontDev &f, T *vr, T *vi, int nrhs);
 
 // z = D^-1 y over the fully-summed positions
 template <typename T>
 __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) {
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s;
-  const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  for (int e = threadIdx.x; e < s * nrhs; e += 256) {
-    const int a = e % s, j = e / s;
-    const int64_t sa = f.soff + a;
-    const int pd = p.pdel[sa];
-    if (pd < 0) continue;
-    const int64_t o = a + (int64_t)j * n;
-    const cd d = p.dinv[sa];
-    const double y0r = vr[o], y0i = vi[o];
-    if (pd == 0) {
-      vr[o] = (T)(d.re * y0r - d.im * y0i);
-      vi[o] = (T)(d.re * y0i + d.im * y0r);
-    } else {
-      const cd d1 = p.dinv[sa + 1], od = p.doff[sa];
-      const double y1r = vr[o + 1], y1i = vi[o + 1];
-      vr[o] = (T)((d.re * y0r - d.im * y0i) + (od.re * y1r - od.im * y1i));
-      vi[o] = (T)((d.re * y0i + d.im * y0r) + (od.re * y1i + od.im * y1r));
-      vr[o + 1] = (T)((od.re * y0r - od.im * y0i) + (d1.re * y1r - d1.im * y1i));
-      vi[o + 1] = (T)((od.re * y0i + od.im * y0r) + (d1.re * y1i + d1.im * y1r));
-    }
-  }
+  T *vi = vr + (int64_t)f.n * p.mr;
+  apply_dinv(p, f, vr, vi, nrhs);
 }
 
 template <typename T>
@@ -934,7 +1015,52 @@ __global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs)
   }
 }
 
-// partial[slot](c, j) = sum_{r in chunk} L(r, k + c) x(r, j)
+// Accumulates sum_{r in [r0, r1)} L(r, k + c) x(r, j) for c = tid % 64 and
+// j = j0 + 4 (tid / 64) + q into (ar, ai), staging 64-row chunks in LDS.
+template <typename T>
+__device__ __forceinline__ void col_dot(T (&lr)[64][NB + 1], T (&li)[64][NB + 1], T (&xr)[64][17], T (&xi)[64][17],
+                                        const T *fr, const T *fi, const T *vr, const T *vi, int n, int k, int b,
+                                        int r0, int r1, int j0, int nrhs, T (&ar)[4], T (&ai)[4]) {
+  const int tid = threadIdx.x, c = tid & 63, jg = tid >> 6;
+  for (int rb = r0; rb < r1; rb += 64) {
+    const int rows = min(64, r1 - rb);
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += 256) {
+      const int m = e % 64, cc = e / 64;
+      T a = 0, bb = 0;
+      if (m < rows && cc < b) {
+        const int64_t o = (rb + m) + (int64_t)(k + cc) * n;
+        a = fr[o];
+        bb = fi[o];
+      }
+      lr[m][cc] = a;
+      li[m][cc] = bb;
+    }
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int m = e % 64, j = e / 64;
+      T a = 0, bb = 0;
+      if (m < rows && j0 + j < nrhs) {
+        const int64_t o = (rb + m) + (int64_t)(j0 + j) * n;
+        a = vr[o];
+        bb = vi[o];
+      }
+      xr[m][j] = a;
+      xi[m][j] = bb;
+    }
+    __syncthreads();
+    for (int m = 0; m < rows; ++m) {
+      const T a = lr[m][c], bb = li[m][c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = jg * 4 + q;
+        ar[q] += a * xr[m][j] - bb * xi[m][j];
+        ai[q] += a * xi[m][j] + bb * xr[m][j];
+      }
+    }
+  }
+}
+
+// partial[slot](c, j) = sum over rows [r0, r0 + 256) of L(r, k + c) x(r, j)
 template <typename T>
 __global__ __launch_bounds__(256) void k_bpart(KP<T> p, int64_t first, int nrhs) {
   __shared__ T lr[64][NB + 1], li[64][NB + 1];
@@ -949,43 +1075,10 @@ __global__ __launch_bounds__(256) void k_bpart(KP<T> p, int64_t first, int nrhs)
   const T *fi = fr + (int64_t)n * n;
   T *pr = p.num + p.part + (int64_t)it.j * NB * mr * 2;
   T *pi = pr + (int64_t)NB * mr;
-  const int rows = min(64, n - r0);
-  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-    const int m = e % 64, c = e / 64;
-    T a = 0, bb = 0;
-    if (m < rows && c < b) {
-      const int64_t o = (r0 + m) + (int64_t)(k + c) * n;
-      a = fr[o];
-      bb = fi[o];
-    }
-    lr[m][c] = a;
-    li[m][c] = bb;
-  }
   const int c = threadIdx.x & 63, jg = threadIdx.x >> 6;
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int m = e % 64, j = e / 64;
-      T a = 0, bb = 0;
-      if (m < rows && j0 + j < nrhs) {
-        const int64_t o = (r0 + m) + (int64_t)(j0 + j) * n;
-        a = vr[o];
-        bb = vi[o];
-      }
-      xr[m][j] = a;
-      xi[m][j] = bb;
-    }
-    __syncthreads();
     T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    for (int m = 0; m < rows; ++m) {
-      const T a = lr[m][c], bb = li[m][c];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = jg * 4 + q;
-        ar[q] += a * xr[m][j] - bb * xi[m][j];
-        ai[q] += a * xi[m][j] + bb * xr[m][j];
-      }
-    }
+    col_dot(lr, li, xr, xi, fr, fi, vr, vi, n, k, b, r0, min(r0 + 256, n), j0, nrhs, ar, ai);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = j0 + jg * 4 + q;
@@ -997,10 +1090,12 @@ __global__ __launch_bounds__(256) void k_bpart(KP<T> p, int64_t first, int nrhs)
   }
 }
 
-// x_k = P_k^T L_kk^-T (z_k - sum partials)
+// v(k + c, j) -= sum_{r >= k+b} L(r, k + c) x(r, j) for the 8 columns
+// c in [c0, c0 + 8) of pivot tile k: 32 lanes per column stride over the rows,
+// the lane sums are reduced through LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bdiag(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T zr[NB][65], zi[NB][65];
+__global__ __launch_bounds__(256) void k_bcol(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T rr_[8][32][17], ri_[8][32][17];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int n = f.n, k = it.k, b = min(NB, f.s - k);
@@ -1009,7 +1104,85 @@ __global__ __launch_bounds__(256) void k_bdiag(KP<T> p, int64_t first, int nrhs)
   T *vi = vr + (int64_t)n * mr;
   const T *fr = p.num + f.off;
   const T *fi = fr + (int64_t)n * n;
-  const int32_t *pm = p.perm + f.soff + k;
+  const int cl = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int c = it.i + cl;
+  const bool live = c < b;
+  const T *Lr = fr + (int64_t)(k + (live ? c : 0)) * n;
+  const T *Li = fi + (int64_t)(k + (live ? c : 0)) * n;
+  for (int j0 = 0; j0 < nrhs; j0 += 16) {
+    const int nj = min(16, nrhs - j0);
+    T ar[16], ai[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ar[q] = ai[q] = 0;
+    if (live) {
+      for (int r = k + b + lane; r < n; r += 32) {
+        const T lr = Lr[r], li = Li[r];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q < nj) {
+            const int64_t o = r + (int64_t)(j0 + q) * n;
+            const T xr = vr[o], xi = vi[o];
+            ar[q] += lr * xr - li * xi;
+            ai[q] += lr * xi + li * xr;
+          }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      rr_[cl][lane][q] = ar[q];
+      ri_[cl][lane][q] = ai[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 * 16) {
+      const int cc = threadIdx.x >> 4, q = threadIdx.x & 15;
+      if (it.i + cc < b && q < nj) {
+        T sr = 0, si = 0;
+#pragma unroll 8
+        for (int l = 0; l < 32; ++l) {
+          sr += rr_[cc][l][q];
+          si += ri_[cc][l][q];
+        }
+        const int64_t o = k + it.i + cc + (int64_t)(j0 + q) * n;
+        vr[o] -= sr;
+        vi[o] -= si;
+      }
+    }
+  }
+}
+
+// x_k = P_k^T L_kk^-T z for columns [j0, j0 + nj) (z in zr/zi, ld 65)
+template <typename T, int ZC>
+__device__ __forceinline__ void tile_backward(const T (&zr)[NB][ZC], const T (&zi)[NB][ZC],
+                                              const T (&yr)[NB][NB + 1], const T (&yi)[NB][NB + 1], T *vr, T *vi,
+                                              int n, int k, int b, const int32_t *pm, int j0, int nj) {
+  for (int e = threadIdx.x; e < b * nj; e += 256) {
+    const int a = e % b, j = e / b;
+    T wr = zr[a][j], wi = zi[a][j];
+    for (int c = a + 1; c < b; ++c) {
+      const T lr = yr[c][a], li = yi[c][a];
+      wr += lr * zr[c][j] - li * zi[c][j];
+      wi += lr * zi[c][j] + li * zr[c][j];
+    }
+    const int64_t o = k + pm[a] + (int64_t)(j0 + j) * n;
+    vr[o] = wr;
+    vi[o] = wi;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bdiag(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T zr[NB][65], zi[NB][65];
+  __shared__ T yr[NB][NB + 1], yi[NB][NB + 1];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, k = it.k, b = min(NB, f.s - k);
+  const int64_t mr = p.mr;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  load_ytile(yr, yi, fr, fi, n, k, b);
   for (int j0 = 0; j0 < nrhs; j0 += 64) {
     const int nj = min(64, nrhs - j0);
     __syncthreads();
@@ -1017,29 +1190,27 @@ __global__ __launch_bounds__(256) void k_bdiag(KP<T> p, int64_t first, int nrhs)
       const int a = e % b, j = e / b;
       const int64_t o = k + a + (int64_t)(j0 + j) * n;
       T sr = vr[o], si = vi[o];
-      for (int sl = 0; sl < it.j; ++sl) {
-        const T *pr = p.num + p.part + (int64_t)(it.i + sl) * NB * mr * 2;
-        const int64_t q = a + (int64_t)(j0 + j) * NB;
-        sr -= pr[q];
-        si -= pr[q + (int64_t)NB * mr];
+      const int64_t q = a + (int64_t)(j0 + j) * NB;
+      const T *pr = p.num + p.part + (int64_t)it.i * NB * mr * 2 + q;
+      const int64_t stride = (int64_t)NB * mr * 2;
+      int sl = 0;
+      for (; sl + 4 <= it.j; sl += 4) {
+        T x0 = pr[(sl + 0) * stride], x1 = pr[(sl + 1) * stride], x2 = pr[(sl + 2) * stride],
+          x3 = pr[(sl + 3) * stride];
+        T y0 = pr[(sl + 0) * stride + NB * mr], y1 = pr[(sl + 1) * stride + NB * mr],
+          y2 = pr[(sl + 2) * stride + NB * mr], y3 = pr[(sl + 3) * stride + NB * mr];
+        sr -= (x0 + x1) + (x2 + x3);
+        si -= (y0 + y1) + (y2 + y3);
+      }
+      for (; sl < it.j; ++sl) {
+        sr -= pr[sl * stride];
+        si -= pr[sl * stride + NB * mr];
       }
       zr[a][j] = sr;
       zi[a][j] = si;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < b * nj; e += 256) {
-      const int a = e % b, j = e / b;
-      T wr = zr[a][j], wi = zi[a][j];
-      for (int c = a + 1; c < b; ++c) {
-        const int64_t o = (k + c) + (int64_t)(k + a) * n;
-        const T lr = fr[o], li = fi[o];
-        wr += lr * zr[c][j] - li * zi[c][j];
-        wi += lr * zi[c][j] + li * zr[c][j];
-      }
-      const int64_t o = k + pm[a] + (int64_t)(j0 + j) * n;
-      vr[o] = wr;
-      vi[o] = wi;
-    }
+    tile_backward(zr, zi, yr, yi, vr, vi, n, k, b, p.perm + f.soff + k, j0, nj);
   }
 }
 
@@ -1063,10 +1234,395 @@ __global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) 
   }
 }
 
-// interface GEMV: mode 0: YG = X v_root ; mode 1: v_root = YG - X h
+// z = D^-1 y over the fully-summed positions of one front (block-wide loop)
+template <typename T>
+__device__ __forceinline__ void apply_dinv(const KP<T> &p, const FrontDev &f, T *vr, T *vi, int nrhs) {
+  const int n = f.n, s = f.s;
+  for (int e = threadIdx.x; e < s * nrhs; e += 256) {
+    const int a = e % s, j = e / s;
+    const int64_t sa = f.soff + a;
+    const int pd = p.pdel[sa];
+    if (pd < 0) continue;
+    const int64_t o = a + (int64_t)j * n;
+    const cd d = p.dinv[sa];
+    const double y0r = vr[o], y0i = vi[o];
+    if (pd == 0) {
+      vr[o] = (T)(d.re * y0r - d.im * y0i);
+      vi[o] = (T)(d.re * y0i + d.im * y0r);
+    } else {
+      const cd d1 = p.dinv[sa + 1], od = p.doff[sa];
+      const double y1r = vr[o + 1], y1i = vi[o + 1];
+      vr[o] = (T)((d.re * y0r - d.im * y0i) + (od.re * y1r - od.im * y1i));
+      vi[o] = (T)((d.re * y0i + d.im * y0r) + (od.re * y1i + od.im * y1r));
+      vr[o + 1] = (T)((od.re * y0r - od.im * y0i) + (d1.re * y1r - d1.im * y1i));
+      vi[o + 1] = (T)((od.re * y0i + od.im * y0r) + (d1.re * y1i + d1.im * y1r));
+    }
+  }
+}
+
+// Whole-front forward substitution in one workgroup (fronts up to FUSE_N):
+// gather + children updates, then per pivot tile y_k = L_kk^-1 P_k v_k and
+// v(rows below) -= L21 y_k, finally z = D^-1 y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ffront(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T sr[NB][65], si[NB][65];
+  __shared__ T yr[NB][NB + 1], yi[NB][NB + 1];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, tid = threadIdx.x;
+  const int64_t mr = p.mr;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  {
+    const bool aux = f.kind == FK_AUX;
+    const int64_t ld = aux ? p.n_mult : p.n_torn;
+    const T *gr = p.num + (aux ? p.vd : p.vf);
+    const T *gi = gr + ld * mr;
+    for (int e = tid; e < n * nrhs; e += 256) {
+      const int r = e % n, j = e / n;
+      T xr = 0, xi = 0;
+      if (r < s) {
+        const int64_t row = f.vbase + p.vars[f.idx + r] + (int64_t)j * ld;
+        xr = gr[row];
+        xi = gi[row];
+      }
+      for (int ch = 0; ch < f.nchild; ++ch) {
+        const int rr = p.rmap[p.crmap[f.child + ch] + r];
+        if (rr < 0) continue;
+        const FrontDev &cf = p.F[p.cfront[f.child + ch]];
+        const int64_t o = cf.voff + cf.s + rr + (int64_t)j * cf.n;
+        xr += p.num[o];
+        xi += p.num[o + (int64_t)cf.n * mr];
+      }
+      vr[r + (int64_t)j * n] = xr;
+      vi[r + (int64_t)j * n] = xi;
+    }
+  }
+  for (int k = 0; k < s; k += NB) {
+    const int b = min(NB, s - k);
+    __syncthreads();
+    load_ytile(yr, yi, fr, fi, n, k, b);
+    for (int j0 = 0; j0 < nrhs; j0 += 64) {
+      const int nj = min(64, nrhs - j0);
+      tile_forward(sr, si, yr, yi, vr, vi, n, k, b, p.perm + f.soff + k, j0, nj);
+      for (int r = k + b + tid; r < n; r += 256) row_update(sr, si, fr, fi, vr, vi, n, k, b, r, j0, nj);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  apply_dinv(p, f, vr, vi, nrhs);
+}
+
+// Whole-front backward substitution in one workgroup: x_R gathered from the
+// global solution, then per pivot tile (descending) x_k = P_k^T L_kk^-T
+// (z_k - L21^T x_below), finally the fully-summed part is scattered.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bfront(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T lr[64][NB + 1], li[64][NB + 1];
+  __shared__ T xr[64][17], xi[64][17];
+  __shared__ T zr[NB][17], zi[NB][17];
+  // the diagonal-tile inverse is staged in the same LDS as the L chunks
+  T (&yr)[NB][NB + 1] = lr;
+  T (&yi)[NB][NB + 1] = li;
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, R = n - s, tid = threadIdx.x;
+  const int64_t mr = p.mr;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  const bool aux = f.kind == FK_AUX;
+  const int64_t ld = aux ? p.n_mult : p.n_torn;
+  {
+    const T *gr = p.num + (aux ? p.vl : p.vx);
+    const T *gi = gr + ld * mr;
+    for (int e = tid; e < R * nrhs; e += 256) {
+      const int r = s + e % R, j = e / R;
+      const int64_t row = f.vbase + p.vars[f.idx + r] + (int64_t)j * ld;
+      vr[r + (int64_t)j * n] = gr[row];
+      vi[r + (int64_t)j * n] = gi[row];
+    }
+  }
+  const int c = tid & 63, jg = tid >> 6;
+  const int T0 = (s + NB - 1) / NB;
+  for (int t = T0 - 1; t >= 0; --t) {
+    const int k = t * NB, b = min(NB, s - k);
+    for (int j0 = 0; j0 < nrhs; j0 += 16) {
+      T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+      col_dot(lr, li, xr, xi, fr, fi, vr, vi, n, k, b, k + b, n, j0, nrhs, ar, ai);
+      __syncthreads();
+      load_ytile(yr, yi, fr, fi, n, k, b);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = jg * 4 + q;
+        T zr_ = 0, zi_ = 0;
+        if (c < b && j0 + j < nrhs) {
+          const int64_t o = k + c + (int64_t)(j0 + j) * n;
+          zr_ = vr[o] - ar[q];
+          zi_ = vi[o] - ai[q];
+        }
+        zr[c][j] = zr_;
+        zi[c][j] = zi_;
+      }
+      __syncthreads();
+      tile_backward(zr, zi, yr, yi, vr, vi, n, k, b, p.perm + f.soff + k, j0, min(16, nrhs - j0));
+    }
+  }
+  __syncthreads();
+  T *dr = p.num + (aux ? p.vl : p.vx);
+  T *di = dr + ld * mr;
+  for (int e = tid; e < s * nrhs; e += 256) {
+    const int r = e % s, j = e / s;
+    const int64_t row = f.vbase + p.vars[f.idx + r] + (int64_t)j * ld;
+    dr[row] = vr[r + (int64_t)j * n];
+    di[row] = vi[r + (int64_t)j * n];
+  }
+}
+
+// Substitutions through a front whose fully-summed block carries Z = L^-1
+// (formed during the factorisation, P basis, lower triangle, unit diagonal).
+// Forward:  y = Z (P v_s) into the W scratch; then v_s = y and v_R -= L21 y.
+// Backward: t = z - L21^T x_R into the W scratch; x_s = P^T Z^T t.
+// Workgroups own 64 rows (or 64 columns); 4 thread groups split the inner
+// dimension and are reduced through LDS.  The right-hand side of the inner
+// products is staged in LDS in chunks of 256.
+template <typename T>
+__device__ __forceinline__ void rows_dot(const KP<T> &p, const FrontDev &f, int r0, int kbeg, int kend, bool tri,
+                                         bool perm_in, const T *inr, const T *ini, int64_t ldin, int j0, int nj,
+                                         T (&ar)[8], T (&ai)[8], T (&sr)[256][9], T (&si)[256][9]) {
+  // ar/ai(q) = sum_{c in [kbeg, kend)} A(r0 + m, c) in(c', j0 + q) for row m = tid % 64
+  // A = Z (tri: c <= r, unit diagonal) or L (front entries); c' = P(c) if perm_in
+  const int n = f.n, m = threadIdx.x & 63, cg = threadIdx.x >> 6, r = r0 + m;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  const int32_t *pm = p.perm + f.soff;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
+  for (int c0 = kbeg; c0 < kend; c0 += 256) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 256 * 8; e += 256) {
+      const int c = e % 256, q = e / 256;
+      T br = 0, bi = 0;
+      if (c0 + c < kend && q < nj) {
+        const int cc = c0 + c;
+        const int src = perm_in ? (cc / NB) * NB + pm[cc] : cc;
+        const int64_t io = src + (int64_t)(j0 + q) * ldin;
+        br = inr[io];
+        bi = ini[io];
+      }
+      sr[c][q] = br;
+      si[c][q] = bi;
+    }
+    __syncthreads();
+    const int cend = min(256, kend - c0);
+    if (r < n) {
+      for (int c = cg; c < cend; c += 4) {
+        const int cc = c0 + c;
+        T xr = 0, xi = 0;
+        if (!tri || cc < r) {
+          const int64_t o = r + (int64_t)cc * n;
+          xr = fr[o];
+          xi = fi[o];
+        } else if (cc == r) {
+          xr = 1;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          ar[q] += xr * sr[c][q] - xi * si[c][q];
+          ai[q] += xr * si[c][q] + xi * sr[c][q];
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void reduce4(T (&ar)[8], T (&ai)[8], T (&rr)[4][64][9], T (&ri)[4][64][9]) {
+  const int m = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    rr[cg][m][q] = ar[q];
+    ri[cg][m][q] = ai[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    ar[q] = rr[0][m][q] + rr[1][m][q] + rr[2][m][q] + rr[3][m][q];
+    ai[q] = ri[0][m][q] + ri[1][m][q] + ri[2][m][q] + ri[3][m][q];
+  }
+}
+
+// y(rows r0..r0+64 of the fully-summed part) = Z (P v_s)  -> W scratch
+template <typename T>
+__global__ __launch_bounds__(256) void k_zfwd(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T sr[256][9], si[256][9];
+  __shared__ T rr[4][64][9], ri[4][64][9];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, r0 = it.i, m = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int64_t mr = p.mr;
+  const T *vr = p.num + f.voff;
+  const T *vi = vr + (int64_t)n * mr;
+  T *Wr = p.num + f.woff;
+  T *Wi = Wr + (int64_t)n * f.wcols;
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    const int nj = min(8, nrhs - j0);
+    T ar[8], ai[8];
+    rows_dot(p, f, r0, 0, min(r0 + 64, s), true, true, vr, vi, n, j0, nj, ar, ai, sr, si);
+    reduce4(ar, ai, rr, ri);
+    if (cg == 0 && r0 + m < s)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nj) {
+          Wr[r0 + m + (int64_t)(j0 + q) * n] = ar[q];
+          Wi[r0 + m + (int64_t)(j0 + q) * n] = ai[q];
+        }
+  }
+}
+
+// rows r0..r0+64: v_s = y (rows < s); v_R -= L21 y (rows >= s)
+template <typename T>
+__global__ __launch_bounds__(256) void k_zfwd2(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T sr[256][9], si[256][9];
+  __shared__ T rr[4][64][9], ri[4][64][9];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, r0 = it.i, m = threadIdx.x & 63, cg = threadIdx.x >> 6, r = r0 + m;
+  const int64_t mr = p.mr;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * mr;
+  const T *Wr = p.num + f.woff;
+  const T *Wi = Wr + (int64_t)n * f.wcols;
+  if (r0 < s) {
+    for (int e = threadIdx.x; e < 64 * nrhs; e += 256) {
+      const int mm = e % 64, j = e / 64;
+      if (r0 + mm < s) {
+        vr[r0 + mm + (int64_t)j * n] = Wr[r0 + mm + (int64_t)j * n];
+        vi[r0 + mm + (int64_t)j * n] = Wi[r0 + mm + (int64_t)j * n];
+      }
+    }
+  }
+  if (r0 + 64 <= s || r0 >= n) return;   // no update rows in this tile (uniform)
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    const int nj = min(8, nrhs - j0);
+    T ar[8], ai[8];
+    rows_dot(p, f, r0, 0, s, false, false, Wr, Wi, n, j0, nj, ar, ai, sr, si);
+    reduce4(ar, ai, rr, ri);
+    if (cg == 0 && r >= s && r < n)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nj) {
+          vr[r + (int64_t)(j0 + q) * n] -= ar[q];
+          vi[r + (int64_t)(j0 + q) * n] -= ai[q];
+        }
+  }
+}
+
+// t(columns c0..c0+64 of the fully-summed part) = z - L21^T x_R -> W scratch
+template <typename T>
+__global__ __launch_bounds__(256) void k_zbwd1(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T lr[64][NB + 1], li[64][NB + 1];
+  __shared__ T xr[64][17], xi[64][17];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, c0 = it.i, b = min(64, s - c0);
+  const int64_t mr = p.mr;
+  const T *vr = p.num + f.voff;
+  const T *vi = vr + (int64_t)n * mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  T *Wr = p.num + f.woff;
+  T *Wi = Wr + (int64_t)n * f.wcols;
+  const int c = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < nrhs; j0 += 16) {
+    T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    if (s < n) col_dot(lr, li, xr, xi, fr, fi, vr, vi, n, c0, b, s, n, j0, nrhs, ar, ai);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + jg * 4 + q;
+      if (c < b && j < nrhs) {
+        const int64_t o = c0 + c + (int64_t)j * n;
+        Wr[o] = vr[o] - ar[q];
+        Wi[o] = vi[o] - ai[q];
+      }
+    }
+  }
+}
+
+// x_s(columns a0..a0+64, P basis) = Z^T t, written un-permuted into v
+template <typename T>
+__global__ __launch_bounds__(256) void k_zbwd2(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T lr[64][NB + 1], li[64][NB + 1];
+  __shared__ T xr[64][17], xi[64][17];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, a0 = it.i, b = min(64, s - a0);
+  const int64_t mr = p.mr;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  const T *Wr = p.num + f.woff;
+  const T *Wi = Wr + (int64_t)n * f.wcols;
+  const int32_t *pm = p.perm + f.soff;
+  const int a = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < nrhs; j0 += 16) {
+    T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    // rows below the diagonal tile: plain column dot with Z
+    if (a0 + 64 < s) col_dot(lr, li, xr, xi, fr, fi, Wr, Wi, n, a0, b, a0 + 64, s, j0, nrhs, ar, ai);
+    // diagonal tile: Z(c, a) for c >= a (unit diagonal)
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int mm = e % 64, j = e / 64;
+      T x0 = 0, x1 = 0;
+      if (mm < b && j0 + j < nrhs) {
+        const int64_t o = a0 + mm + (int64_t)(j0 + j) * n;
+        x0 = Wr[o];
+        x1 = Wi[o];
+      }
+      xr[mm][j] = x0;
+      xi[mm][j] = x1;
+    }
+    __syncthreads();
+    if (a < b) {
+      for (int c = a; c < b; ++c) {
+        T zr = 1, zi = 0;
+        if (c > a) {
+          const int64_t o = (a0 + c) + (int64_t)(a0 + a) * n;
+          zr = fr[o];
+          zi = fi[o];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = jg * 4 + q;
+          ar[q] += zr * xr[c][j] - zi * xi[c][j];
+          ai[q] += zr * xi[c][j] + zi * xr[c][j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + jg * 4 + q;
+        if (j < nrhs) {
+          const int64_t o = (a0 / NB) * NB + pm[a0 + a] + (int64_t)j * n;
+          vr[o] = ar[q];
+          vi[o] = ai[q];
+        }
+      }
+    }
+  }
+}
+
+// interface GEMV: mode 0: YG = X v_root ; mode 1: v_root = YG - X h.
+// Workgroup = 64 rows x 4 column groups; the right-hand side is staged in LDS
+// in chunks of 256 columns of X.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
   __shared__ T redr[4][64][9], redi[4][64][9];
+  __shared__ T inr_s[256][9], ini_s[256][9];
   const Item it = p.gemv[blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int g = f.s;
@@ -1089,20 +1645,33 @@ __global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
     outr = v; outi = v + (int64_t)g * mr;
   }
   for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    const int nj = min(8, nrhs - j0);
     T ar[8], ai[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
-    if (r < g) {
-      for (int c = cg; c < g; c += 4) {
-        const int64_t o = r + (int64_t)c * g;
-        const T xr = Xr[o], xi = Xi[o];
+    for (int c0 = 0; c0 < g; c0 += 256) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < 256 * 8; e += 256) {
+        const int c = e % 256, q = e / 256;
+        T br = 0, bi = 0;
+        if (c0 + c < g && q < nj) {
+          const int64_t io = c0 + c + (int64_t)(j0 + q) * g;
+          br = inr[io];
+          bi = ini[io];
+        }
+        inr_s[c][q] = br;
+        ini_s[c][q] = bi;
+      }
+      __syncthreads();
+      if (r < g) {
+        const int cend = min(256, g - c0);
+        for (int c = cg; c < cend; c += 4) {
+          const int64_t o = r + (int64_t)(c0 + c) * g;
+          const T xr = Xr[o], xi = Xi[o];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (j0 + q < nrhs) {
-            const int64_t io = c + (int64_t)(j0 + q) * g;
-            const T br = inr[io], bi = ini[io];
-            ar[q] += xr * br - xi * bi;
-            ai[q] += xr * bi + xi * br;
+          for (int q = 0; q < 8; ++q) {
+            ar[q] += xr * inr_s[c][q] - xi * ini_s[c][q];
+            ai[q] += xr * ini_s[c][q] + xi * inr_s[c][q];
           }
         }
       }
@@ -1116,7 +1685,7 @@ __global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
     if (cg == 0 && r < g) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        if (j0 + q >= nrhs) break;
+        if (q >= nj) break;
         T sr = redr[0][m][q] + redr[1][m][q] + redr[2][m][q] + redr[3][m][q];
         T si = redi[0][m][q] + redi[1][m][q] + redi[2][m][q] + redi[3][m][q];
         const int64_t o = r + (int64_t)(j0 + q) * g;
@@ -1129,7 +1698,6 @@ __global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
         }
       }
     }
-    __syncthreads();
   }
 }
 
@@ -1258,70 +1826,98 @@ __global__ void k_r_update(KP<T> p, int nrhs) {
 }
 
 // r_u = f - K u - B^T lam ; r_l = -B u ; writes the FP32 correction rhs (vf, vc)
-// and per-block sums of |r|^2 (or |f|^2 when fnorm) per column
+// and per-block sums of |r|^2 (or |f|^2 when fnorm) per column.  Columns are
+// processed 8 at a time so the operator is streamed once per 8 columns.
 template <typename T>
 __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t ldf, int nrhs, int64_t part_off,
                                                  int fnorm) {
-  __shared__ double red[256];
+  __shared__ double red[8][256];
   const int64_t mr = p.mr;
   const double *U = p.r64;
   const double *L = U + 2 * p.n_torn * mr;
   double *part = p.r64 + part_off;
   const int64_t nrow = p.n_torn + p.n_mult;
-  for (int j = 0; j < nrhs; ++j) {
-    double acc = 0;
+  const int64_t nt = p.n_torn, nm = p.n_mult;
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    const int nj = min(8, nrhs - j0);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nrow; e += (int64_t)gridDim.x * 256) {
-      double rr, ri;
-      if (e < p.n_torn) {
-        const cd fv = f[e + j * ldf];
-        rr = fv.re;
-        ri = fv.im;
-        if (!fnorm) {
-          for (int64_t q = p.csrp[e]; q < p.csrp[e + 1]; ++q) {
-            const cd a = p.vals[q];
-            const int64_t c = p.csrc[q];
-            const double ur = U[c + j * p.n_torn], ui = U[c + j * p.n_torn + p.n_torn * mr];
-            rr -= a.re * ur - a.im * ui;
-            ri -= a.re * ui + a.im * ur;
+      double rr[8], ri[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rr[q] = ri[q] = 0;
+      if (e < nt) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nj) {
+            const cd fv = f[e + (j0 + q) * ldf];
+            rr[q] = fv.re;
+            ri[q] = fv.im;
           }
-          const int g = p.rowgam[e];
-          if (g >= 0) {
-            const GamRef G = p.grefs[g];
+        if (!fnorm) {
+          for (int64_t z = p.csrp[e]; z < p.csrp[e + 1]; ++z) {
+            const cd a = p.vals[z];
+            const int64_t c = p.csrc[z];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (q < nj) {
+                const double ur = U[c + (j0 + q) * nt], ui = U[c + (j0 + q) * nt + nt * mr];
+                rr[q] -= a.re * ur - a.im * ui;
+                ri[q] -= a.re * ui + a.im * ur;
+              }
+          }
+          const int gidx = p.rowgam[e];
+          if (gidx >= 0) {
+            const GamRef G = p.grefs[gidx];
             for (int t = 0; t < G.cnt; ++t) {
               const int64_t m = p.hmult[G.beg + t];
-              const double s = p.hsign[G.beg + t];
-              rr -= s * L[m + j * p.n_mult];
-              ri -= s * L[m + j * p.n_mult + p.n_mult * mr];
+              const double sg = p.hsign[G.beg + t];
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (q < nj) {
+                  rr[q] -= sg * L[m + (j0 + q) * nm];
+                  ri[q] -= sg * L[m + (j0 + q) * nm + nm * mr];
+                }
             }
           }
           T *vf = p.num + p.vf;
-          vf[e + j * p.n_torn] = (T)rr;
-          vf[e + j * p.n_torn + p.n_torn * mr] = (T)ri;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (q < nj) {
+              vf[e + (j0 + q) * nt] = (T)rr[q];
+              vf[e + (j0 + q) * nt + nt * mr] = (T)ri[q];
+            }
         }
-      } else {
-        if (fnorm) continue;
-        const int64_t m = e - p.n_torn;
+      } else if (!fnorm) {
+        const int64_t m = e - nt;
         const MultRef R = p.mrefs[m];
-        rr = 0;
-        ri = 0;
-        for (int t = 0; t < 2; ++t) {
-          const double s = R.sg[t];
-          rr -= s * U[R.row[t] + j * p.n_torn];
-          ri -= s * U[R.row[t] + j * p.n_torn + p.n_torn * mr];
-        }
         T *vc = p.num + p.vc;
-        vc[m + j * p.n_mult] = (T)rr;
-        vc[m + j * p.n_mult + p.n_mult * mr] = (T)ri;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nj) {
+            for (int t = 0; t < 2; ++t) {
+              const double sg = R.sg[t];
+              rr[q] -= sg * U[R.row[t] + (j0 + q) * nt];
+              ri[q] -= sg * U[R.row[t] + (j0 + q) * nt + nt * mr];
+            }
+            vc[m + (j0 + q) * nm] = (T)rr[q];
+            vc[m + (j0 + q) * nm + nm * mr] = (T)ri[q];
+          }
       }
-      acc += rr * rr + ri * ri;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += rr[q] * rr[q] + ri[q] * ri[q];
     }
-    red[threadIdx.x] = acc;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x + (int64_t)j * gridDim.x] = red[0];
+    if (threadIdx.x < nj) part[blockIdx.x + (int64_t)(j0 + threadIdx.x) * gridDim.x] = red[threadIdx.x][0];
     __syncthreads();
   }
 }
@@ -1423,8 +2019,8 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_PANEL: hipLaunchKernelGGL(k_panel<T>, g, b, 0, st, k, L.first); break;
       case L_TRSM: hipLaunchKernelGGL(k_trsm<T>, g, b, 0, st, k, L.first); break;
       case L_SYRK: hipLaunchKernelGGL(k_syrk<T>, g, b, 0, st, k, L.first); break;
-      case L_INVPREP: hipLaunchKernelGGL(k_invprep<T>, g, b, 0, st, k, L.first); break;
-      case L_INVTRMM: hipLaunchKernelGGL(k_invtrmm<T>, g, b, 0, st, k, L.first); break;
+      case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
+      case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
       case L_INVSYRK: hipLaunchKernelGGL(k_invsyrk<T>, g, b, 0, st, k, L.first); break;
       case S_FINIT: hipLaunchKernelGGL(k_finit<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_FDIAG: hipLaunchKernelGGL(k_fdiag<T>, g, b, 0, st, k, L.first, nrhs); break;
@@ -1434,6 +2030,13 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case S_BPART: hipLaunchKernelGGL(k_bpart<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_BDIAG: hipLaunchKernelGGL(k_bdiag<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_BFIN: hipLaunchKernelGGL(k_bfin<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_FFRONT: hipLaunchKernelGGL(k_ffront<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_BCOL: hipLaunchKernelGGL(k_bcol<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZFWD: hipLaunchKernelGGL(k_zfwd<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZFWD2: hipLaunchKernelGGL(k_zfwd2<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZBWD1: hipLaunchKernelGGL(k_zbwd1<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZBWD2: hipLaunchKernelGGL(k_zbwd2<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_BFRONT: hipLaunchKernelGGL(k_bfront<T>, g, b, 0, st, k, L.first, nrhs); break;
       default: return hipErrorInvalidValue;
     }
     if (timed) {
@@ -1444,11 +2047,15 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
   return hipGetLastError();
 }
 
+// clears the status words (a kernel, so that graph capture records no memset)
+__global__ void k_zero_status(int *status) {
+  if (threadIdx.x < 2) status[threadIdx.x] = 0;
+}
+
 template <typename T>
 static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm) {
   KP<T> k = make_kp<T>(P, ws, vals);
-  hipError_t e = hipMemsetAsync(k.status, 0, 2 * sizeof(int), st);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, k.status);
   return run_seq<T>(P, k, P.factor_seq, 0, st, tm);
 }
 

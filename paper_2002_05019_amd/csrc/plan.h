@@ -18,8 +18,8 @@ enum LaunchKind : int32_t {
   L_PANEL,      // pivot-tile LDL^T with restricted Bunch-Kaufman
   L_TRSM,       // W = A21 P L11^-T, L21 = W D^-1
   L_SYRK,       // trailing update C -= L21 W^T
-  L_INVPREP,    // W' = P L21 L11^-1
-  L_INVTRMM,    // Z21 = -Z22 W'
+  L_ZREC1,      // recursive inverse: T1 = P L21 Z11 (upper triangle)
+  L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
   L_INVSYRK,    // X = P^T Z^T D^-1 Z P
   // solve
   S_FINIT, S_FDIAG, S_FUPD, S_FFIN,
@@ -27,6 +27,13 @@ enum LaunchKind : int32_t {
   S_MGATHER,    // d = sum_i B_i y_i - c
   S_HGATHER,    // h = B_Gamma^T lambda
   S_BINIT, S_BPART, S_BDIAG, S_BFIN,
+  S_FFRONT,     // whole-front forward substitution, one workgroup per front
+  S_BFRONT,     // whole-front backward substitution, one workgroup per front
+  S_BCOL,       // pivot-tile right-hand side -= L21^T x (8 columns per workgroup)
+  S_ZFWD,       // y = Z P v_s for fronts carrying Z = L11^-1
+  S_ZFWD2,      // v_s = y, v_R -= L21 y
+  S_ZBWD1,      // t = z - L21^T x_R
+  S_ZBWD2,      // x_s = P^T Z^T t
 };
 
 struct Launch {

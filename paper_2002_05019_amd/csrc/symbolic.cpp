@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <utility>
@@ -900,14 +901,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         const double b = std::min(NB, d.s - it.k);
         return 8.0 * (b * b * b / 3.0 + b * b * b / 6.0);
       }
-      case L_INVPREP: {
-        const double rows = std::min(GT, n - it.i);
-        return 8.0 * rows * NB * (NB + 1) / 2;
+      case L_ZREC1: {   // T1 tile: rows x cols x K (K from the column tile to m0)
+        const double rows = std::min(GT, d.s - it.i), cols = std::min(GT, it.k - it.j);
+        return 8.0 * rows * cols * (it.k - it.j - cols / 2);
       }
-      case L_INVTRMM: {
-        const double rows = std::min(GT, n - it.i);
-        const double kl = std::max(0, std::min(it.i + GT, n) - (it.k + NB));
-        return 8.0 * rows * NB * (kl - rows / 2);
+      case L_ZREC2: {
+        const double rows = std::min(GT, d.s - it.i), cols = std::min(GT, it.k - it.j);
+        return 8.0 * rows * cols * (it.i - it.k + rows / 2);
       }
       case L_INVSYRK: {
         const double rows = std::min(GT, n - it.i), cols = std::min(GT, n - it.j);
@@ -929,7 +929,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     L.flops = 0;
     if (kind <= L_INVSYRK)
       for (const Item &it : its) L.flops += item_flops(kind, it);
-    const bool gemm = kind == L_SYRK || kind == L_TRSM || kind == L_INVPREP || kind == L_INVTRMM || kind == L_INVSYRK;
+    const bool gemm = kind == L_SYRK || kind == L_TRSM || kind == L_ZREC1 || kind == L_ZREC2 || kind == L_INVSYRK;
     if (gemm && its.size() >= 16) {
       // Workgroup b runs on XCD b % 8: give each XCD a contiguous run of the
       // item list (items sharing an operand panel are adjacent), so that
@@ -988,7 +988,8 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     std::vector<Item> as, sc, ag;
     for (int f : fs) {
       const FrontDev &d = P.fronts[f];
-      for (int c0 = 0; c0 < d.n; c0 += 64) as.push_back({f, c0, 0, 0});
+      for (int c0 = 0; c0 < d.n; c0 += 64)
+        for (int r0 = c0; r0 < d.n; r0 += 256) as.push_back({f, c0, r0, 0});
       if (!aux) {
         auto pr = prange[f];
         for (int64_t b = 0; b < pr.second; b += 4096)
@@ -1014,6 +1015,41 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     for (auto &kv : lv) out.push_back(kv.second);
     return out;
   };
+  // Z = L11^-1 of the fully-summed block (P basis) by recursive halving of
+  // the tile range; all splits of one height (over all fronts) form one pair
+  // of launches.  The single tiles already hold L_kk^-1.
+  auto zsteps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
+    std::map<int, std::vector<std::array<int, 4>>> by_h;   // height -> (f, a, m, b) in tiles
+    std::function<int(int, int, int)> rec = [&](int f, int a, int b) -> int {
+      if (b - a <= 1) return 0;
+      const int m = (a + b) / 2;
+      const int h = 1 + std::max(rec(f, a, m), rec(f, m, b));
+      by_h[h].push_back({f, a, m, b});
+      return h;
+    };
+    for (int f : fs) rec(f, 0, ntiles(P.fronts[f].s, NB));
+    for (auto &kv : by_h) {
+      std::vector<Item> g1, g2;
+      for (auto &nd : kv.second) {
+        const FrontDev &d = P.fronts[nd[0]];
+        const int c0 = nd[1] * NB, m0 = nd[2] * NB, r1 = std::min(nd[3] * NB, d.s);
+        for (int r = m0; r < r1; r += GT)
+          for (int c = c0; c < m0; c += GT) {
+            g1.push_back({nd[0], m0, r, c});
+            g2.push_back({nd[0], m0, r, c});
+          }
+      }
+      push(seq, L_ZREC1, g1);
+      push(seq, L_ZREC2, g2);
+    }
+  };
+  auto zfront = [&](int f) { return P.fronts[f].kind != FK_GAMMA && P.fronts[f].n > FUSE_N; };
+  auto zset = [&](const std::vector<int> &lv) {
+    std::vector<int> z;
+    for (int f : lv)
+      if (zfront(f)) z.push_back(f);
+    return z;
+  };
   std::vector<std::vector<int>> dom_levels = by_height(FK_INTERIOR, FK_INTERIOR, false);
   std::vector<int> gam;
   for (int i = 0; i < p.n_dom; ++i)
@@ -1025,26 +1061,12 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   for (auto &lv : dom_levels) {
     assemble(P.factor_seq, lv, false);
     factor_steps(P.factor_seq, lv);
+    zsteps(P.factor_seq, zset(lv));
   }
   if (!gam.empty()) {
     assemble(P.factor_seq, gam, false);
     factor_steps(P.factor_seq, gam);
-    int maxt = 0;
-    for (int f : gam) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
-    for (int t = 0; t + 1 < maxt; ++t) {
-      std::vector<Item> pr;
-      for (int f : gam) {
-        const FrontDev &d = P.fronts[f];
-        int T = ntiles(d.s, NB);
-        int kt = T - 2 - t;
-        if (kt < 0) continue;
-        int k = kt * NB;
-        int r0 = k + NB;
-        for (int r = r0; r < d.s; r += GT) pr.push_back({f, k, r, 0});
-      }
-      push(P.factor_seq, L_INVPREP, pr);
-      push(P.factor_seq, L_INVTRMM, pr);
-    }
+    zsteps(P.factor_seq, gam);
     std::vector<Item> sy;
     for (int f : gam) {
       const FrontDev &d = P.fronts[f];
@@ -1057,60 +1079,60 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   for (auto &lv : aux_levels) {
     assemble(P.factor_seq, lv, true);
     factor_steps(P.factor_seq, lv);
+    zsteps(P.factor_seq, zset(lv));
   }
 
   // solve: forward over a set of levels
   int64_t max_part = 0;
+  // Small fronts: one workgroup per front.  Fronts carrying Z = L11^-1:
+  // a few row/column-parallel triangular products per front.
   auto fwd = [&](std::vector<Launch> &seq, const std::vector<std::vector<int>> &levels, bool gamma_only_init) {
     for (auto &lv : levels) {
-      std::vector<Item> in;
-      for (int f : lv) in.push_back({f, 0, 0, 0});
-      push(seq, S_FINIT, in);
-      if (gamma_only_init) continue;
-      int maxt = 0;
-      for (int f : lv) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
-      for (int t = 0; t < maxt; ++t) {
-        std::vector<Item> dg, up;
-        for (int f : lv) {
-          const FrontDev &d = P.fronts[f];
-          int k = t * NB;
-          if (k >= d.s) continue;
-          int b = std::min(NB, d.s - k);
-          dg.push_back({f, k, 0, 0});
-          for (int r = k + b; r < d.n; r += 256) up.push_back({f, k, r, 0});
+      std::vector<Item> small, in, zf, zf2;
+      for (int f : lv) {
+        const FrontDev &d = P.fronts[f];
+        if (gamma_only_init) {
+          in.push_back({f, 0, 0, 0});
+          continue;
         }
-        push(seq, S_FDIAG, dg);
-        push(seq, S_FUPD, up);
+        if (!zfront(f)) {
+          small.push_back({f, 0, 0, 0});
+          continue;
+        }
+        in.push_back({f, 0, 0, 0});
+        for (int r = 0; r < d.s; r += 64) zf.push_back({f, 0, r, 0});
+        for (int r = 0; r < d.n; r += 64) zf2.push_back({f, 0, r, 0});
       }
-      push(seq, S_FFIN, in);
+      push(seq, S_FFRONT, small);
+      push(seq, S_FINIT, in);
+      push(seq, S_ZFWD, zf);
+      push(seq, S_ZFWD2, zf2);
+      if (!gamma_only_init) {
+        std::vector<Item> fin;
+        for (auto &it : in) fin.push_back(it);
+        push(seq, S_FFIN, fin);
+      }
     }
   };
   auto bwd = [&](std::vector<Launch> &seq, const std::vector<std::vector<int>> &levels) {
     for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
-      auto &lv = *it;
-      std::vector<Item> in;
-      for (int f : lv) in.push_back({f, 0, 0, 0});
-      push(seq, S_BINIT, in);
-      int maxt = 0;
-      for (int f : lv) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
-      for (int t = 0; t < maxt; ++t) {
-        std::vector<Item> pa, dg;
-        int slot = 0;
-        for (int f : lv) {
-          const FrontDev &d = P.fronts[f];
-          int T = ntiles(d.s, NB);
-          int kt = T - 1 - t;
-          if (kt < 0) continue;
-          int k = kt * NB;
-          int b = std::min(NB, d.s - k);
-          int s0 = slot;
-          for (int r = k + b; r < d.n; r += 64) pa.push_back({f, k, r, slot++});
-          dg.push_back({f, k, s0, slot - s0});
+      std::vector<Item> small, in, zb1, zb2;
+      for (int f : *it) {
+        const FrontDev &d = P.fronts[f];
+        if (!zfront(f)) {
+          small.push_back({f, 0, 0, 0});
+          continue;
         }
-        max_part = std::max<int64_t>(max_part, slot);
-        push(seq, S_BPART, pa);
-        push(seq, S_BDIAG, dg);
+        in.push_back({f, 0, 0, 0});
+        for (int c = 0; c < d.s; c += 64) {
+          zb1.push_back({f, 0, c, 0});
+          zb2.push_back({f, 0, c, 0});
+        }
       }
+      push(seq, S_BFRONT, small);
+      push(seq, S_BINIT, in);
+      push(seq, S_ZBWD1, zb1);
+      push(seq, S_ZBWD2, zb2);
       push(seq, S_BFIN, in);
     }
   };

@@ -113,3 +113,31 @@ def test_refactor_same_context():
     s.factor(vals2)
     u = s.solve(_rhs(c))
     assert _colerr(u.cpu().numpy(), 0.5 * _ref("cube6")["u"]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_graph_replay_bitwise_equals_eager(precision):
+    """Factor + solve replayed from hipGraphs, three times with eager work and
+    synchronisations in between, equal bit for bit to the eager launches."""
+    c = cached_case("cube16")
+    eager = _solver(c, precision=precision)
+    f = _rhs(c)
+    ue = eager.solve(f).cpu().numpy()
+    s = _solver(c, precision=precision, use_graph=True)
+    vals = torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV)
+    for rep in range(3):
+        s.factor(vals)
+        u = s.solve(f).cpu().numpy()
+        assert np.array_equal(u, ue), (rep, np.abs(u - ue).max())
+        eager.factor(vals)
+        ue2 = eager.solve(f).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(ue2, ue)
+    assert s.info()["n_perturbed"] == 0
+
+
+def test_repeat_runs_bitwise_identical():
+    c = cached_case("cube18u")
+    a = _solver(c).solve(_rhs(c)).cpu().numpy()
+    b = _solver(c).solve(_rhs(c)).cpu().numpy()
+    assert np.array_equal(a, b)
