@@ -14,6 +14,7 @@ constexpr int NB = 64;        // pivot-tile width of the blocked LDL^T
 constexpr int GT = 64;        // output tile edge of the MFMA GEMMs
 constexpr int KBLK = 256;     // outer block (columns per trailing update)
 constexpr int FUSE_N = 384;    // fronts up to this size are substituted by one workgroup
+constexpr int ZKC = 256;      // K chunk of the split substitution products
 
 enum FrontKind : int32_t { FK_INTERIOR = 0, FK_GAMMA = 1, FK_AUX = 2 };
 

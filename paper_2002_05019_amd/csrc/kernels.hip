@@ -294,226 +294,276 @@ __global__ __launch_bounds__(256) void k_auxg(KP<T> p, int64_t first) {
 }
 
 // ---------------------------------------------------------------------------
-// pivot tile: restricted Bunch-Kaufman LDL^T of the NB x NB diagonal tile, in
-// FP64 in LDS (both triangles kept), with L^-1 formed alongside.
-__device__ __forceinline__ void wave_argmax(double &v, int &idx) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off);
-    const int oi = __shfl_xor(idx, off);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
-    }
-  }
-}
+// pivot tile: restricted Bunch-Kaufman LDL^T of the NB x NB diagonal tile in
+// FP64, with L^-1 formed alongside (section II: pivot search confined to the
+// diagonal block).  The tile and L^-1 stay in registers, 2-D cyclic over a
+// 16 x 16 thread grid: thread (tr, tc) holds entries (tr + 16u, tc + 16v),
+// both triangles, in their original (physical) positions.  Interchanges are
+// never carried out on the data: the logical order is a permutation kept
+// per lane (lane a of every wave holds the physical index of position a),
+// and the not yet eliminated physical rows form a bit mask.  Per step only
+// the pivot column(s) and the matching rows of L^-1 pass through LDS; every
+// wave repeats the pivot search (identical result), so a step without a
+// rejected diagonal needs two barriers.
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
   return v;
 }
+// a[w] for a block-uniform w in [0, 4) without dynamic register indexing
+__device__ __forceinline__ double pick4(double a0, double a1, double a2, double a3, int w) {
+  double r = a0;
+  r = w == 1 ? a1 : r;
+  r = w == 2 ? a2 : r;
+  r = w == 3 ? a3 : r;
+  return r;
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel(KP<T> p, int64_t first) {
-  __shared__ double Ar[NB][NB + 1], Ai[NB][NB + 1];
-  __shared__ double Yr[NB][NB + 1], Yi[NB][NB + 1];
-  __shared__ double v0r[NB], v0i[NB], v1r[NB], v1i[NB], l0r[NB], l0i[NB], l1r[NB], l1i[NB];
+  __shared__ double cjr[NB], cji[NB], c1r[NB], c1i[NB], ckr[NB], cki[NB];
+  __shared__ double yjr[NB], yji[NB], y1r[NB], y1i[NB];
   __shared__ double dvr[NB], dvi[NB], dor[NB], doi[NB];
-  __shared__ int pdl[NB], pv[NB];
-  __shared__ int s_kind, s_piv, s_pert;
-  __shared__ double s_amax;
+  __shared__ int pdl[NB], inv[NB];
+  __shared__ double red[4];
 
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int k = it.k, n = f.n, b = min(NB, f.s - k), tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4, lane = tid & 63;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
   constexpr double ALPHA = 0.6403882032022076;   // (1 + sqrt(17)) / 8
 
+  double ar[4][4], ai[4][4], yr[4][4], yi[4][4];
   double amax = 0;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    if (i < b && j < b && i >= j) {
-      const int64_t o = (k + i) + (int64_t)(k + j) * n;
-      const double xr = (double)fr[o], xi = (double)fi[o];
-      Ar[i][j] = xr;
-      Ai[i][j] = xi;
-      Ar[j][i] = xr;
-      Ai[j][i] = xi;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = tr + 16 * u, c = tc + 16 * v;
+      double xr = 0, xi = 0;
+      if (i < b && c < b) {
+        const int64_t o = (k + max(i, c)) + (int64_t)(k + min(i, c)) * n;
+        xr = (double)fr[o];
+        xi = (double)fi[o];
+      }
+      ar[u][v] = xr;
+      ai[u][v] = xi;
       amax = fmax(amax, cabs1(xr, xi));
+      yr[u][v] = i == c ? 1.0 : 0.0;
+      yi[u][v] = 0.0;
     }
-    if (i < NB && j < NB) {
-      Yr[i][j] = (i == j) ? 1.0 : 0.0;
-      Yi[i][j] = 0.0;
-    }
-  }
-  if (tid < NB) pv[tid] = tid;
-  // block max for the perturbation scale
-  {
-    __shared__ double red[4];
-    amax = wave_max(amax);
-    if ((tid & 63) == 0) red[tid >> 6] = amax;
-    __syncthreads();
-    if (tid == 0) {
-      s_amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-      s_pert = 0;
-    }
-    __syncthreads();
-  }
-  const double tau = s_amax > 0 ? 1e-12 * s_amax : 1.0;
+  amax = wave_max(amax);
+  if (lane == 0) red[tid >> 6] = amax;
+  __syncthreads();
+  const double tmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double tau = tmax > 0 ? 1e-12 * tmax : 1.0;
 
+  // column col of the tile -> (dr, di)[physical row]; row row of L^-1 -> (er, ei)
+  auto put_col = [&](int col, double *dr, double *di) {
+    if (tc == (col & 15)) {
+      const int w = col >> 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        dr[tr + 16 * u] = pick4(ar[u][0], ar[u][1], ar[u][2], ar[u][3], w);
+        di[tr + 16 * u] = pick4(ai[u][0], ai[u][1], ai[u][2], ai[u][3], w);
+      }
+    }
+  };
+  auto put_yrow = [&](int row, double *er, double *ei) {
+    if (tr == (row & 15)) {
+      const int w = row >> 4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        er[tc + 16 * v] = pick4(yr[0][v], yr[1][v], yr[2][v], yr[3][v], w);
+        ei[tc + 16 * v] = pick4(yi[0][v], yi[1][v], yi[2][v], yi[3][v], w);
+      }
+    }
+  };
+
+  int pv = lane;                                          // physical row at position `lane`
+  uint64_t alive = b == 64 ? ~0ull : ((1ull << b) - 1);   // physical rows not yet eliminated
+  int npert = 0;
   int j = 0;
   while (j < b) {
-    if (tid < 64) {
-      const int i = tid;
-      const double absakk = cabs1(Ar[j][j], Ai[j][j]);
-      double cv = (i > j && i < b) ? cabs1(Ar[i][j], Ai[i][j]) : -1.0;
-      int imax = i;
-      wave_argmax(cv, imax);
-      const double colmax = cv;
-      int kind = 1, piv = j;
-      if (colmax > 0.0 && absakk < ALPHA * colmax) {
-        double rv = (i >= j && i < b && i != imax) ? cabs1(Ar[imax][i], Ai[imax][i]) : -1.0;
-        const double rowmax = wave_max(rv);
-        if (absakk * rowmax >= ALPHA * colmax * colmax) {
-          kind = 1;
-          piv = j;
-        } else if (cabs1(Ar[imax][imax], Ai[imax][imax]) >= ALPHA * rowmax) {
-          kind = 1;
-          piv = imax;
-        } else {
-          kind = 2;
-          piv = imax;
-        }
-      }
-      if (tid == 0) {
-        s_kind = kind;
-        s_piv = piv;
-      }
-    }
+    int pj = __builtin_amdgcn_readlane(pv, j);
+    put_col(pj, cjr, cji);
+    put_yrow(pj, yjr, yji);
     __syncthreads();
-    const int kind = s_kind, piv = s_piv;
-    const int q = (kind == 1) ? j : j + 1;
+    // pivot choice over positions j.. (physical rows pv), in every wave
+    const double absakk = cabs1(cjr[pj], cji[pj]);
+    const bool cand = lane > j && lane < b;
+    const double cv = cand ? cabs1(cjr[pv], cji[pv]) : -1.0;
+    const double colmax = wave_max(cv);
+    int kind = 1, piv = j;
+    if (__builtin_amdgcn_readfirstlane(colmax > 0.0 && absakk < ALPHA * colmax)) {
+      // lowest position attaining the column maximum
+      const int imax = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)__ballot(cand && cv == colmax)) - 1);
+      const int pm = __builtin_amdgcn_readlane(pv, imax);
+      put_col(pm, ckr, cki);
+      __syncthreads();
+      const double rv = (lane >= j && lane < b && lane != imax) ? cabs1(ckr[pv], cki[pv]) : -1.0;
+      const double rowmax = wave_max(rv);
+      if (absakk * rowmax >= ALPHA * colmax * colmax) {
+        kind = 1;
+        piv = j;
+      } else if (cabs1(ckr[pm], cki[pm]) >= ALPHA * rowmax) {
+        kind = 1;
+        piv = imax;
+      } else {
+        kind = 2;
+        piv = imax;
+      }
+      kind = __builtin_amdgcn_readfirstlane(kind);
+      piv = __builtin_amdgcn_readfirstlane(piv);
+    }
+    const int q = kind == 1 ? j : j + 1;
     if (piv != q) {
-      for (int c = tid; c < b; c += 256) {
-        double t = Ar[q][c]; Ar[q][c] = Ar[piv][c]; Ar[piv][c] = t;
-        t = Ai[q][c]; Ai[q][c] = Ai[piv][c]; Ai[piv][c] = t;
+      // interchange of positions q and piv: only the order changes
+      const int a0 = __builtin_amdgcn_readlane(pv, q), a1 = __builtin_amdgcn_readlane(pv, piv);
+      pv = lane == q ? a1 : (lane == piv ? a0 : pv);
+      if (kind == 1) {
+        // the new pivot column (old column piv) is in ck; L^-1 row again
+        pj = a1;
+        put_yrow(pj, yjr, yji);
+        __syncthreads();
       }
-      for (int c = tid; c < j; c += 256) {
-        double t = Yr[q][c]; Yr[q][c] = Yr[piv][c]; Yr[piv][c] = t;
-        t = Yi[q][c]; Yi[q][c] = Yi[piv][c]; Yi[piv][c] = t;
-      }
-      if (tid == 0) {
-        int t = pv[q]; pv[q] = pv[piv]; pv[piv] = t;
-      }
-      __syncthreads();
-      for (int r = j + tid; r < b; r += 256) {
-        double t = Ar[r][q]; Ar[r][q] = Ar[r][piv]; Ar[r][piv] = t;
-        t = Ai[r][q]; Ai[r][q] = Ai[r][piv]; Ai[r][piv] = t;
-      }
-      __syncthreads();
     }
     if (kind == 1) {
-      double dr = Ar[j][j], di = Ai[j][j];
+      // pivot column: cj, or ck after an interchange (it holds column pm)
+      const double *qr_ = piv != q ? ckr : cjr, *pi_ = piv != q ? cki : cji;
+      double dr = qr_[pj], di = pi_[pj];
       if (dr == 0.0 && di == 0.0) {
         dr = tau;
-        if (tid == 0) s_pert++;
+        ++npert;
       }
       const double den = dr * dr + di * di;
       const double ir = dr / den, ii = -di / den;
-      for (int i = j + 1 + tid; i < b; i += 256) {
-        const double vr = Ar[i][j], vi = Ai[i][j];
-        v0r[i] = vr;
-        v0i[i] = vi;
-        l0r[i] = vr * ir - vi * ii;
-        l0i[i] = vr * ii + vi * ir;
-      }
       if (tid == 0) {
         dvr[j] = ir; dvi[j] = ii; dor[j] = 0; doi[j] = 0; pdl[j] = 0;
       }
-      __syncthreads();
-      const int m = b - j - 1;
-      for (int e = tid; e < m * m; e += 256) {
-        const int i = j + 1 + e % m, c = j + 1 + e / m;
-        Ar[i][c] -= v0r[i] * l0r[c] - v0i[i] * l0i[c];
-        Ai[i][c] -= v0r[i] * l0i[c] + v0i[i] * l0r[c];
+      alive &= ~(1ull << pj);
+      // A(r, c) -= l(r) A(c, pj), L^-1(r, :) -= l(r) L^-1(pj, :) over alive r, c
+      double lr[4], li[4], wr[4], wi[4], er[4], ei[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = tr + 16 * u;
+        const bool ok = (alive >> i) & 1;
+        const double xr = ok ? qr_[i] : 0.0, xi = ok ? pi_[i] : 0.0;
+        lr[u] = xr * ir - xi * ii;
+        li[u] = xr * ii + xi * ir;
       }
-      for (int e = tid; e < m * (j + 1); e += 256) {
-        const int i = j + 1 + e % m, c = e / m;
-        const double yr = Yr[j][c], yi = Yi[j][c];
-        Yr[i][c] -= l0r[i] * yr - l0i[i] * yi;
-        Yi[i][c] -= l0r[i] * yi + l0i[i] * yr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = tc + 16 * v;
+        const bool ok = (alive >> c) & 1;
+        wr[v] = ok ? qr_[c] : 0.0;
+        wi[v] = ok ? pi_[c] : 0.0;
+        er[v] = yjr[c];
+        ei[v] = yji[c];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          ar[u][v] -= lr[u] * wr[v] - li[u] * wi[v];
+          ai[u][v] -= lr[u] * wi[v] + li[u] * wr[v];
+          yr[u][v] -= lr[u] * er[v] - li[u] * ei[v];
+          yi[u][v] -= lr[u] * ei[v] + li[u] * er[v];
+        }
       __syncthreads();
       j += 1;
     } else {
-      double ar = Ar[j][j], ai = Ai[j][j], cr = Ar[j + 1][j], ci = Ai[j + 1][j];
-      double er = Ar[j + 1][j + 1], ei = Ai[j + 1][j + 1];
-      double detr = (ar * er - ai * ei) - (cr * cr - ci * ci);
-      double deti = (ar * ei + ai * er) - 2.0 * cr * ci;
+      const int p1 = __builtin_amdgcn_readlane(pv, j + 1);
+      put_col(p1, c1r, c1i);
+      put_yrow(p1, y1r, y1i);
+      __syncthreads();
+      double ar_ = cjr[pj], ai_ = cji[pj], cr = cjr[p1], ci = cji[p1];
+      double er_ = c1r[p1], ei_ = c1i[p1];
+      double detr = (ar_ * er_ - ai_ * ei_) - (cr * cr - ci * ci);
+      double deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr * ci;
       if (detr == 0.0 && deti == 0.0) {
-        ar += tau;
-        er += tau;
-        detr = (ar * er - ai * ei) - (cr * cr - ci * ci);
-        deti = (ar * ei + ai * er) - 2.0 * cr * ci;
-        if (tid == 0) s_pert++;
+        ar_ += tau;
+        er_ += tau;
+        detr = (ar_ * er_ - ai_ * ei_) - (cr * cr - ci * ci);
+        deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr * ci;
+        ++npert;
       }
       const double den = detr * detr + deti * deti;
       const double idr = detr / den, idi = -deti / den;   // 1/det
       // D^-1 = [[e, -c], [-c, a]] / det
-      const double d00r = er * idr - ei * idi, d00i = er * idi + ei * idr;
-      const double d11r = ar * idr - ai * idi, d11i = ar * idi + ai * idr;
+      const double d00r = er_ * idr - ei_ * idi, d00i = er_ * idi + ei_ * idr;
+      const double d11r = ar_ * idr - ai_ * idi, d11i = ar_ * idi + ai_ * idr;
       const double d01r = -(cr * idr - ci * idi), d01i = -(cr * idi + ci * idr);
-      for (int i = j + 2 + tid; i < b; i += 256) {
-        const double xr = Ar[i][j], xi = Ai[i][j], yr = Ar[i][j + 1], yi = Ai[i][j + 1];
-        v0r[i] = xr; v0i[i] = xi; v1r[i] = yr; v1i[i] = yi;
-        l0r[i] = (xr * d00r - xi * d00i) + (yr * d01r - yi * d01i);
-        l0i[i] = (xr * d00i + xi * d00r) + (yr * d01i + yi * d01r);
-        l1r[i] = (xr * d01r - xi * d01i) + (yr * d11r - yi * d11i);
-        l1i[i] = (xr * d01i + xi * d01r) + (yr * d11i + yi * d11r);
-      }
       if (tid == 0) {
         dvr[j] = d00r; dvi[j] = d00i; dvr[j + 1] = d11r; dvi[j + 1] = d11i;
         dor[j] = d01r; doi[j] = d01i; dor[j + 1] = d01r; doi[j + 1] = d01i;
         pdl[j] = 1; pdl[j + 1] = -1;
       }
-      __syncthreads();
-      const int m = b - j - 2;
-      for (int e = tid; e < m * m; e += 256) {
-        const int i = j + 2 + e % m, c = j + 2 + e / m;
-        Ar[i][c] -= (v0r[i] * l0r[c] - v0i[i] * l0i[c]) + (v1r[i] * l1r[c] - v1i[i] * l1i[c]);
-        Ai[i][c] -= (v0r[i] * l0i[c] + v0i[i] * l0r[c]) + (v1r[i] * l1i[c] + v1i[i] * l1r[c]);
+      alive &= ~((1ull << pj) | (1ull << p1));
+      // [l0 l1](r) = [A(r, pj) A(r, p1)] D^-1;
+      // A(r, c) -= l0(r) A(c, pj) + l1(r) A(c, p1); L^-1(r, :) -= l0(r) L^-1(pj, :) + l1(r) L^-1(p1, :)
+      double l0r[4], l0i[4], l1r[4], l1i[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = tr + 16 * u;
+        const bool ok = (alive >> i) & 1;
+        const double a0r = ok ? cjr[i] : 0.0, a0i = ok ? cji[i] : 0.0;
+        const double a1r = ok ? c1r[i] : 0.0, a1i = ok ? c1i[i] : 0.0;
+        l0r[u] = (a0r * d00r - a0i * d00i) + (a1r * d01r - a1i * d01i);
+        l0i[u] = (a0r * d00i + a0i * d00r) + (a1r * d01i + a1i * d01r);
+        l1r[u] = (a0r * d01r - a0i * d01i) + (a1r * d11r - a1i * d11i);
+        l1i[u] = (a0r * d01i + a0i * d01r) + (a1r * d11i + a1i * d11r);
       }
-      for (int e = tid; e < m * (j + 2); e += 256) {
-        const int i = j + 2 + e % m, c = e / m;
-        const double y0r = Yr[j][c], y0i = Yi[j][c], y1r = Yr[j + 1][c], y1i = Yi[j + 1][c];
-        Yr[i][c] -= (l0r[i] * y0r - l0i[i] * y0i) + (l1r[i] * y1r - l1i[i] * y1i);
-        Yi[i][c] -= (l0r[i] * y0i + l0i[i] * y0r) + (l1r[i] * y1i + l1i[i] * y1r);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = tc + 16 * v;
+        const bool ok = (alive >> c) & 1;
+        const double w0r = ok ? cjr[c] : 0.0, w0i = ok ? cji[c] : 0.0;
+        const double w1r = ok ? c1r[c] : 0.0, w1i = ok ? c1i[c] : 0.0;
+        const double e0r = yjr[c], e0i = yji[c], e1r = y1r[c], e1i = y1i[c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ar[u][v] -= (l0r[u] * w0r - l0i[u] * w0i) + (l1r[u] * w1r - l1i[u] * w1i);
+          ai[u][v] -= (l0r[u] * w0i + l0i[u] * w0r) + (l1r[u] * w1i + l1i[u] * w1r);
+          yr[u][v] -= (l0r[u] * e0r - l0i[u] * e0i) + (l1r[u] * e1r - l1i[u] * e1i);
+          yi[u][v] -= (l0r[u] * e0i + l0i[u] * e0r) + (l1r[u] * e1i + l1i[u] * e1r);
+        }
       }
       __syncthreads();
       j += 2;
     }
   }
-  // write L^-1 into the strict lower triangle of the diagonal tile
-  for (int e = tid; e < b * b; e += 256) {
-    const int i = e % b, c = e / b;
-    if (i > c) {
-      const int64_t o = (k + i) + (int64_t)(k + c) * n;
-      fr[o] = (T)Yr[i][c];
-      fi[o] = (T)Yi[i][c];
+  // L^-1 in the pivoted order into the strict lower triangle of the tile:
+  // position (a, c) is physical (pv[a], pv[c])
+  if (tid < 64) inv[pv] = lane;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = tr + 16 * u, c = tc + 16 * v;
+      if (i < b && c < b) {
+        const int a = inv[i], cc = inv[c];
+        if (cc < a) {
+          const int64_t o = (k + a) + (int64_t)(k + cc) * n;
+          fr[o] = (T)yr[u][v];
+          fi[o] = (T)yi[u][v];
+        }
+      }
     }
-  }
   bool bad = false;
-  for (int a = tid; a < b; a += 256) {
-    const int64_t s = f.soff + k + a;
-    p.dinv[s] = cd{dvr[a], dvi[a]};
-    p.doff[s] = cd{dor[a], doi[a]};
-    p.pdel[s] = pdl[a];
-    p.perm[s] = pv[a];
-    if (!isfinite(dvr[a]) || !isfinite(dvi[a])) bad = true;
+  if (tid < b) {
+    const int64_t s = f.soff + k + tid;
+    p.dinv[s] = cd{dvr[tid], dvi[tid]};
+    p.doff[s] = cd{dor[tid], doi[tid]};
+    p.pdel[s] = pdl[tid];
+    p.perm[s] = pv;
+    if (!isfinite(dvr[tid]) || !isfinite(dvi[tid])) bad = true;
   }
   if (bad) atomicOr(p.status + 1, 1);
-  if (tid == 0 && s_pert) atomicAdd(p.status, s_pert);
+  if (tid == 0 && npert) atomicAdd(p.status, npert);
 }
 
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
@@ -796,11 +846,14 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
 
 // ---------------------------------------------------------------------------
 // multi-RHS substitutions (front vectors v: n x mr planar, ld n)
+// Front vector rows [it.i, it.i + 256): gathered right-hand side on the
+// fully-summed rows plus the children's update parts (extend-add).
 template <typename T>
 __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs) {
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s;
+  const int n = f.n, s = f.s, r = it.i + threadIdx.x;
+  if (r >= n) return;
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * mr;
@@ -808,24 +861,101 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
   const int64_t ld = aux ? p.n_mult : p.n_torn;
   const T *sr = p.num + (aux ? p.vd : p.vf);
   const T *si = sr + ld * mr;
-  for (int e = threadIdx.x; e < n * nrhs; e += 256) {
-    const int r = e % n, j = e / n;
+  const int64_t row = r < s ? f.vbase + p.vars[f.idx + r] : -1;
+  for (int j = 0; j < nrhs; ++j) {
     T xr = 0, xi = 0;
-    if (r < s) {
-      const int64_t row = f.vbase + p.vars[f.idx + r] + (int64_t)j * ld;
-      xr = sr[row];
-      xi = si[row];
-    }
-    for (int ch = 0; ch < f.nchild; ++ch) {
-      const int rr = p.rmap[p.crmap[f.child + ch] + r];
-      if (rr < 0) continue;
-      const FrontDev &cf = p.F[p.cfront[f.child + ch]];
-      const int64_t o = cf.voff + cf.s + rr + (int64_t)j * cf.n;
-      xr += p.num[o];
-      xi += p.num[o + (int64_t)cf.n * mr];
+    if (row >= 0) {
+      xr = sr[row + (int64_t)j * ld];
+      xi = si[row + (int64_t)j * ld];
     }
     vr[r + (int64_t)j * n] = xr;
     vi[r + (int64_t)j * n] = xi;
+  }
+  for (int ch = 0; ch < f.nchild; ++ch) {
+    const int rr = p.rmap[p.crmap[f.child + ch] + r];
+    if (rr < 0) continue;
+    const FrontDev &cf = p.F[p.cfront[f.child + ch]];
+    const T *cr = p.num + cf.voff + cf.s + rr;
+    const T *ci = cr + (int64_t)cf.n * mr;
+    for (int j = 0; j < nrhs; ++j) {
+      vr[r + (int64_t)j * n] += cr[(int64_t)j * cf.n];
+      vi[r + (int64_t)j * n] += ci[(int64_t)j * cf.n];
+    }
+  }
+}
+
+// z = D^-1 y on the fully-summed rows [it.i, it.i + 256) (a 2 x 2 block is
+// applied by the thread of its first row).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) {
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, a = it.i + threadIdx.x;
+  if (a >= f.s) return;
+  const int64_t sa = f.soff + a;
+  const int pd = p.pdel[sa];
+  if (pd < 0) return;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * p.mr;
+  const cd d = p.dinv[sa];
+  const cd d1 = pd ? p.dinv[sa + 1] : cd{0, 0}, od = pd ? p.doff[sa] : cd{0, 0};
+  for (int j = 0; j < nrhs; ++j) {
+    const int64_t o = a + (int64_t)j * n;
+    const double y0r = vr[o], y0i = vi[o];
+    if (pd == 0) {
+      vr[o] = (T)(d.re * y0r - d.im * y0i);
+      vi[o] = (T)(d.re * y0i + d.im * y0r);
+    } else {
+      const double y1r = vr[o + 1], y1i = vi[o + 1];
+      vr[o] = (T)((d.re * y0r - d.im * y0i) + (od.re * y1r - od.im * y1i));
+      vi[o] = (T)((d.re * y0i + d.im * y0r) + (od.re * y1i + od.im * y1r));
+      vr[o + 1] = (T)((od.re * y0r - od.im * y0i) + (d1.re * y1r - d1.im * y1i));
+      vi[o + 1] = (T)((od.re * y0i + od.im * y0r) + (d1.re * y1i + d1.im * y1r));
+    }
+  }
+}
+
+// Update rows [it.i, it.i + 256) (>= s) of the front vector from the global
+// solution vector.
+template <typename T>
+__global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs) {
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, r = it.i + threadIdx.x;
+  if (r >= n) return;
+  const int64_t mr = p.mr;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * mr;
+  const bool aux = f.kind == FK_AUX;
+  const int64_t ld = aux ? p.n_mult : p.n_torn;
+  const T *sr = p.num + (aux ? p.vl : p.vx);
+  const T *si = sr + ld * mr;
+  const int64_t row = f.vbase + p.vars[f.idx + r];
+  for (int j = 0; j < nrhs; ++j) {
+    vr[r + (int64_t)j * n] = sr[row + (int64_t)j * ld];
+    vi[r + (int64_t)j * n] = si[row + (int64_t)j * ld];
+  }
+}
+
+// Fully-summed rows [it.i, it.i + 256) of the front vector to the global
+// solution vector.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) {
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, r = it.i + threadIdx.x;
+  if (r >= f.s) return;
+  const int64_t mr = p.mr;
+  const T *vr = p.num + f.voff;
+  const T *vi = vr + (int64_t)n * mr;
+  const bool aux = f.kind == FK_AUX;
+  const int64_t ld = aux ? p.n_mult : p.n_torn;
+  T *dr = p.num + (aux ? p.vl : p.vx);
+  T *di = dr + ld * mr;
+  const int64_t row = f.vbase + p.vars[f.idx + r];
+  for (int j = 0; j < nrhs; ++j) {
+    dr[row + (int64_t)j * ld] = vr[r + (int64_t)j * n];
+    di[row + (int64_t)j * ld] = vi[r + (int64_t)j * n];
   }
 }
 
@@ -936,85 +1066,6 @@ __device__ __forceinline__ void row_update(const T (&sr)[NB][65], const T (&si)[
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_fdiag(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T sr[NB][65], si[NB][65];
-  __shared__ T yr[NB][NB + 1], yi[NB][NB + 1];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, k = it.k, b = min(NB, f.s - k);
-  const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
-  load_ytile(yr, yi, fr, fi, n, k, b);
-  for (int j0 = 0; j0 < nrhs; j0 += 64) {
-    const int nj = min(64, nrhs - j0);
-    tile_forward(sr, si, yr, yi, vr, vi, n, k, b, p.perm + f.soff + k, j0, nj);
-  }
-}
-
-// v(rows r0..r0+255, r >= k+b) -= L21(:, tile k) y_k
-template <typename T>
-__global__ __launch_bounds__(256) void k_fupd(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T sr[NB][65], si[NB][65];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, k = it.k, b = min(NB, f.s - k);
-  const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
-  const int r = it.i + threadIdx.x;
-  for (int j0 = 0; j0 < nrhs; j0 += 64) {
-    const int nj = min(64, nrhs - j0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * nj; e += 256) {
-      const int a = e % b, j = e / b;
-      const int64_t o = k + a + (int64_t)(j0 + j) * n;
-      sr[a][j] = vr[o];
-      si[a][j] = vi[o];
-    }
-    __syncthreads();
-    if (r < n) row_update(sr, si, fr, fi, vr, vi, n, k, b, r, j0, nj);
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void apply_dinv(const KP<T> &p, const FrontDev &f, T *vr, T *vi, int nrhs);
-
-// z = D^-1 y over the fully-summed positions
-template <typename T>
-__global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) {
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)f.n * p.mr;
-  apply_dinv(p, f, vr, vi, nrhs);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs) {
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, R = n - s;
-  const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  const bool aux = f.kind == FK_AUX;
-  const int64_t ld = aux ? p.n_mult : p.n_torn;
-  const T *sr = p.num + (aux ? p.vl : p.vx);
-  const T *si = sr + ld * mr;
-  for (int e = threadIdx.x; e < R * nrhs; e += 256) {
-    const int r = s + e % R, j = e / R;
-    const int64_t row = f.vbase + p.vars[f.idx + r] + (int64_t)j * ld;
-    vr[r + (int64_t)j * n] = sr[row];
-    vi[r + (int64_t)j * n] = si[row];
-  }
-}
-
 // Accumulates sum_{r in [r0, r1)} L(r, k + c) x(r, j) for c = tid % 64 and
 // j = j0 + 4 (tid / 64) + q into (ar, ai), staging 64-row chunks in LDS.
 template <typename T>
@@ -1060,97 +1111,6 @@ __device__ __forceinline__ void col_dot(T (&lr)[64][NB + 1], T (&li)[64][NB + 1]
   }
 }
 
-// partial[slot](c, j) = sum over rows [r0, r0 + 256) of L(r, k + c) x(r, j)
-template <typename T>
-__global__ __launch_bounds__(256) void k_bpart(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T lr[64][NB + 1], li[64][NB + 1];
-  __shared__ T xr[64][17], xi[64][17];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, k = it.k, b = min(NB, f.s - k), r0 = it.i;
-  const int64_t mr = p.mr;
-  const T *vr = p.num + f.voff;
-  const T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
-  T *pr = p.num + p.part + (int64_t)it.j * NB * mr * 2;
-  T *pi = pr + (int64_t)NB * mr;
-  const int c = threadIdx.x & 63, jg = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    col_dot(lr, li, xr, xi, fr, fi, vr, vi, n, k, b, r0, min(r0 + 256, n), j0, nrhs, ar, ai);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + jg * 4 + q;
-      if (c < b && j < nrhs) {
-        pr[c + (int64_t)j * NB] = ar[q];
-        pi[c + (int64_t)j * NB] = ai[q];
-      }
-    }
-  }
-}
-
-// v(k + c, j) -= sum_{r >= k+b} L(r, k + c) x(r, j) for the 8 columns
-// c in [c0, c0 + 8) of pivot tile k: 32 lanes per column stride over the rows,
-// the lane sums are reduced through LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void k_bcol(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T rr_[8][32][17], ri_[8][32][17];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, k = it.k, b = min(NB, f.s - k);
-  const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
-  const int cl = threadIdx.x >> 5, lane = threadIdx.x & 31;
-  const int c = it.i + cl;
-  const bool live = c < b;
-  const T *Lr = fr + (int64_t)(k + (live ? c : 0)) * n;
-  const T *Li = fi + (int64_t)(k + (live ? c : 0)) * n;
-  for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    const int nj = min(16, nrhs - j0);
-    T ar[16], ai[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) ar[q] = ai[q] = 0;
-    if (live) {
-      for (int r = k + b + lane; r < n; r += 32) {
-        const T lr = Lr[r], li = Li[r];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (q < nj) {
-            const int64_t o = r + (int64_t)(j0 + q) * n;
-            const T xr = vr[o], xi = vi[o];
-            ar[q] += lr * xr - li * xi;
-            ai[q] += lr * xi + li * xr;
-          }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      rr_[cl][lane][q] = ar[q];
-      ri_[cl][lane][q] = ai[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < 8 * 16) {
-      const int cc = threadIdx.x >> 4, q = threadIdx.x & 15;
-      if (it.i + cc < b && q < nj) {
-        T sr = 0, si = 0;
-#pragma unroll 8
-        for (int l = 0; l < 32; ++l) {
-          sr += rr_[cc][l][q];
-          si += ri_[cc][l][q];
-        }
-        const int64_t o = k + it.i + cc + (int64_t)(j0 + q) * n;
-        vr[o] -= sr;
-        vi[o] -= si;
-      }
-    }
-  }
-}
-
 // x_k = P_k^T L_kk^-T z for columns [j0, j0 + nj) (z in zr/zi, ld 65)
 template <typename T, int ZC>
 __device__ __forceinline__ void tile_backward(const T (&zr)[NB][ZC], const T (&zi)[NB][ZC],
@@ -1167,70 +1127,6 @@ __device__ __forceinline__ void tile_backward(const T (&zr)[NB][ZC], const T (&z
     const int64_t o = k + pm[a] + (int64_t)(j0 + j) * n;
     vr[o] = wr;
     vi[o] = wi;
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_bdiag(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T zr[NB][65], zi[NB][65];
-  __shared__ T yr[NB][NB + 1], yi[NB][NB + 1];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, k = it.k, b = min(NB, f.s - k);
-  const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
-  load_ytile(yr, yi, fr, fi, n, k, b);
-  for (int j0 = 0; j0 < nrhs; j0 += 64) {
-    const int nj = min(64, nrhs - j0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * nj; e += 256) {
-      const int a = e % b, j = e / b;
-      const int64_t o = k + a + (int64_t)(j0 + j) * n;
-      T sr = vr[o], si = vi[o];
-      const int64_t q = a + (int64_t)(j0 + j) * NB;
-      const T *pr = p.num + p.part + (int64_t)it.i * NB * mr * 2 + q;
-      const int64_t stride = (int64_t)NB * mr * 2;
-      int sl = 0;
-      for (; sl + 4 <= it.j; sl += 4) {
-        T x0 = pr[(sl + 0) * stride], x1 = pr[(sl + 1) * stride], x2 = pr[(sl + 2) * stride],
-          x3 = pr[(sl + 3) * stride];
-        T y0 = pr[(sl + 0) * stride + NB * mr], y1 = pr[(sl + 1) * stride + NB * mr],
-          y2 = pr[(sl + 2) * stride + NB * mr], y3 = pr[(sl + 3) * stride + NB * mr];
-        sr -= (x0 + x1) + (x2 + x3);
-        si -= (y0 + y1) + (y2 + y3);
-      }
-      for (; sl < it.j; ++sl) {
-        sr -= pr[sl * stride];
-        si -= pr[sl * stride + NB * mr];
-      }
-      zr[a][j] = sr;
-      zi[a][j] = si;
-    }
-    __syncthreads();
-    tile_backward(zr, zi, yr, yi, vr, vi, n, k, b, p.perm + f.soff + k, j0, nj);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) {
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s;
-  const int64_t mr = p.mr;
-  const T *vr = p.num + f.voff;
-  const T *vi = vr + (int64_t)n * mr;
-  const bool aux = f.kind == FK_AUX;
-  const int64_t ld = aux ? p.n_mult : p.n_torn;
-  T *dr = p.num + (aux ? p.vl : p.vx);
-  T *di = dr + ld * mr;
-  for (int e = threadIdx.x; e < s * nrhs; e += 256) {
-    const int r = e % s, j = e / s;
-    const int64_t row = f.vbase + p.vars[f.idx + r] + (int64_t)j * ld;
-    dr[row] = vr[r + (int64_t)j * n];
-    di[row] = vi[r + (int64_t)j * n];
   }
 }
 
@@ -1382,236 +1278,217 @@ __global__ __launch_bounds__(256) void k_bfront(KP<T> p, int64_t first, int nrhs
   }
 }
 
-// Substitutions through a front whose fully-summed block carries Z = L^-1
-// (formed during the factorisation, P basis, lower triangle, unit diagonal).
-// Forward:  y = Z (P v_s) into the W scratch; then v_s = y and v_R -= L21 y.
-// Backward: t = z - L21^T x_R into the W scratch; x_s = P^T Z^T t.
-// Workgroups own 64 rows (or 64 columns); 4 thread groups split the inner
-// dimension and are reduced through LDS.  The right-hand side of the inner
-// products is staged in LDS in chunks of 256.
+// Substitutions through a front whose fully-summed block carries Z = L11^-1
+// (formed during the factorisation, P basis, strict lower triangle, unit
+// diagonal), as split products: every item computes one 64-output tile over
+// one K chunk of ZKC into its own partial slot (64 x mr, planar), and the
+// reduction kernel sums a tile's slots in a fixed order (deterministic) and
+// applies the epilogue.
+//   M = 0: y(r) = sum_{c <= r} Z(r, c) v(P c)        r < s        -> W, v_s
+//   M = 1: u(r) = sum_{c < s}  L(r, c) y(c)          s <= r < n   -> v_R -= u
+//   M = 2: u(c) = sum_{s <= r < n} L(r, c) x(r)      c < s        -> W = z - u
+//   M = 3: x(a) = sum_{c >= a} Z(c, a) t(c)          a < s        -> v(P a)
+// The right-hand sides are processed 8 at a time; an input row is staged in
+// LDS as 16 contiguous values (8 real parts, then 8 imaginary parts) and read
+// back with 16-byte broadcasts.
 template <typename T>
-__device__ __forceinline__ void rows_dot(const KP<T> &p, const FrontDev &f, int r0, int kbeg, int kend, bool tri,
-                                         bool perm_in, const T *inr, const T *ini, int64_t ldin, int j0, int nj,
-                                         T (&ar)[8], T (&ai)[8], T (&sr)[256][9], T (&si)[256][9]) {
-  // ar/ai(q) = sum_{c in [kbeg, kend)} A(r0 + m, c) in(c', j0 + q) for row m = tid % 64
-  // A = Z (tri: c <= r, unit diagonal) or L (front entries); c' = P(c) if perm_in
-  const int n = f.n, m = threadIdx.x & 63, cg = threadIdx.x >> 6, r = r0 + m;
+__device__ __forceinline__ void zacc(const T *x, T ar_, T ai_, T (&ar)[8], T (&ai)[8]) {
+  T xv[16];
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float4 w = reinterpret_cast<const float4 *>(x)[u];
+      xv[4 * u] = w.x; xv[4 * u + 1] = w.y; xv[4 * u + 2] = w.z; xv[4 * u + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double2 w = reinterpret_cast<const double2 *>(x)[u];
+      xv[2 * u] = w.x; xv[2 * u + 1] = w.y;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    ar[q] += ar_ * xv[q] - ai_ * xv[8 + q];
+    ai[q] += ar_ * xv[8 + q] + ai_ * xv[q];
+  }
+}
+
+// Sums the four thread groups' accumulators (through red, 4 x 64 x 16) and
+// writes RHS columns [j0, j0 + 8) of the 64-output partial slot.
+template <typename T>
+__device__ __forceinline__ void zpart_out(T *red, const T (&ar)[8], const T (&ai)[8], T *slot, int64_t mr, int j0,
+                                          int nrhs) {
+  const int tid = threadIdx.x, o = tid & 63, g = tid >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    red[(g * 64 + o) * 16 + q] = ar[q];
+    red[(g * 64 + o) * 16 + 8 + q] = ai[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = g + 4 * h;
+    if (j0 + q < nrhs) {
+      T sr = 0, si = 0;
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        sr += red[(gg * 64 + o) * 16 + q];
+        si += red[(gg * 64 + o) * 16 + 8 + q];
+      }
+      slot[(int64_t)(j0 + q) * 64 + o] = sr;
+      slot[64 * mr + (int64_t)(j0 + q) * 64 + o] = si;
+    }
+  }
+}
+
+// M = 0, 1: lanes own output rows (coalesced matrix loads), the four thread
+// groups stride over the K chunk.
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_zprod_n(KP<T> p, int64_t first, int nrhs) {
+  __shared__ __align__(16) T xs[ZKC * 16];
+  __shared__ __align__(16) T red[4 * 64 * 16];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, i0 = it.i, c0 = it.j, tid = threadIdx.x;
+  const int o = tid & 63, g = tid >> 6, r = i0 + o;
+  const int cend = min(c0 + ZKC, M == 0 ? min(s, i0 + 64) : s);
+  const int64_t mr = p.mr;
   const T *fr = p.num + f.off;
   const T *fi = fr + (int64_t)n * n;
+  const T *inr = M == 0 ? p.num + f.voff : p.num + f.woff;
+  const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
   const int32_t *pm = p.perm + f.soff;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
-  for (int c0 = kbeg; c0 < kend; c0 += 256) {
+  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
+  const bool live = M == 0 ? r < s : r < n;
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 256 * 8; e += 256) {
-      const int c = e % 256, q = e / 256;
+    for (int e = tid; e < ZKC * 8; e += 256) {
+      const int c = e % ZKC, q = e / ZKC, cc = c0 + c;
       T br = 0, bi = 0;
-      if (c0 + c < kend && q < nj) {
-        const int cc = c0 + c;
-        const int src = perm_in ? (cc / NB) * NB + pm[cc] : cc;
-        const int64_t io = src + (int64_t)(j0 + q) * ldin;
+      if (cc < cend && j0 + q < nrhs) {
+        const int src = M == 0 ? (cc / NB) * NB + pm[cc] : cc;
+        const int64_t io = src + (int64_t)(j0 + q) * n;
         br = inr[io];
         bi = ini[io];
       }
-      sr[c][q] = br;
-      si[c][q] = bi;
+      xs[c * 16 + q] = br;
+      xs[c * 16 + 8 + q] = bi;
     }
     __syncthreads();
-    const int cend = min(256, kend - c0);
-    if (r < n) {
-      for (int c = cg; c < cend; c += 4) {
-        const int cc = c0 + c;
-        T xr = 0, xi = 0;
-        if (!tri || cc < r) {
-          const int64_t o = r + (int64_t)cc * n;
-          xr = fr[o];
-          xi = fi[o];
-        } else if (cc == r) {
-          xr = 1;
-        }
+    T ar[8], ai[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          ar[q] += xr * sr[c][q] - xi * si[c][q];
-          ai[q] += xr * si[c][q] + xi * sr[c][q];
+    for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
+    if (live) {
+#pragma unroll 4
+      for (int c = c0 + g; c < cend; c += 4) {
+        T zr = 0, zi = 0;
+        if (M != 0 || c < r) {
+          const int64_t e = r + (int64_t)c * n;
+          zr = fr[e];
+          zi = fi[e];
+        } else if (c == r) {
+          zr = 1;
         }
+        zacc(&xs[(c - c0) * 16], zr, zi, ar, ai);
       }
     }
+    zpart_out(red, ar, ai, slot, mr, j0, nrhs);
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void reduce4(T (&ar)[8], T (&ai)[8], T (&rr)[4][64][9], T (&ri)[4][64][9]) {
-  const int m = threadIdx.x & 63, cg = threadIdx.x >> 6;
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    rr[cg][m][q] = ar[q];
-    ri[cg][m][q] = ai[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    ar[q] = rr[0][m][q] + rr[1][m][q] + rr[2][m][q] + rr[3][m][q];
-    ai[q] = ri[0][m][q] + ri[1][m][q] + ri[2][m][q] + ri[3][m][q];
-  }
-}
-
-// y(rows r0..r0+64 of the fully-summed part) = Z (P v_s)  -> W scratch
-template <typename T>
-__global__ __launch_bounds__(256) void k_zfwd(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T sr[256][9], si[256][9];
-  __shared__ T rr[4][64][9], ri[4][64][9];
+// M = 2, 3: lanes own output columns; 64 x 64 matrix tiles are staged in LDS
+// with coalesced loads, the four thread groups split the tile's rows.
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_zprod_t(KP<T> p, int64_t first, int nrhs) {
+  __shared__ T at[2][64][65];
+  __shared__ __align__(16) T xs[64 * 16];
+  T *red = &at[0][0][0];   // 4 x 64 x 16 <= 2 x 64 x 65
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, r0 = it.i, m = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int n = f.n, s = f.s, i0 = it.i, k0 = it.j, tid = threadIdx.x;
+  const int o = tid & 63, g = tid >> 6;
+  const int kend = min(k0 + ZKC, M == 2 ? n : s);
   const int64_t mr = p.mr;
-  const T *vr = p.num + f.voff;
-  const T *vi = vr + (int64_t)n * mr;
-  T *Wr = p.num + f.woff;
-  T *Wi = Wr + (int64_t)n * f.wcols;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
+  const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
+  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
   for (int j0 = 0; j0 < nrhs; j0 += 8) {
-    const int nj = min(8, nrhs - j0);
     T ar[8], ai[8];
-    rows_dot(p, f, r0, 0, min(r0 + 64, s), true, true, vr, vi, n, j0, nj, ar, ai, sr, si);
-    reduce4(ar, ai, rr, ri);
-    if (cg == 0 && r0 + m < s)
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nj) {
-          Wr[r0 + m + (int64_t)(j0 + q) * n] = ar[q];
-          Wi[r0 + m + (int64_t)(j0 + q) * n] = ai[q];
+    for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
+    for (int rb = k0; rb < kend; rb += 64) {
+      __syncthreads();
+      for (int e = tid; e < 64 * 64; e += 256) {
+        const int rr = e & 63, cc = e >> 6, row = rb + rr, col = i0 + cc;
+        T vr = 0, vi = 0;
+        if (row < kend && col < s) {
+          if (M == 2 || row > col) {
+            const int64_t x = row + (int64_t)col * n;
+            vr = fr[x];
+            vi = fi[x];
+          } else if (row == col) {
+            vr = 1;
+          }
         }
+        at[0][rr][cc] = vr;
+        at[1][rr][cc] = vi;
+      }
+      for (int e = tid; e < 64 * 8; e += 256) {
+        const int rr = e & 63, q = e >> 6, row = rb + rr;
+        T br = 0, bi = 0;
+        if (row < kend && j0 + q < nrhs) {
+          const int64_t x = row + (int64_t)(j0 + q) * n;
+          br = inr[x];
+          bi = ini[x];
+        }
+        xs[rr * 16 + q] = br;
+        xs[rr * 16 + 8 + q] = bi;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int rr = g * 16; rr < g * 16 + 16; ++rr) zacc(&xs[rr * 16], at[0][rr][o], at[1][rr][o], ar, ai);
+    }
+    zpart_out(red, ar, ai, slot, mr, j0, nrhs);
   }
 }
 
-// rows r0..r0+64: v_s = y (rows < s); v_R -= L21 y (rows >= s)
-template <typename T>
-__global__ __launch_bounds__(256) void k_zfwd2(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T sr[256][9], si[256][9];
-  __shared__ T rr[4][64][9], ri[4][64][9];
+// Reduction of the partial slots [it.k, it.k + it.j) of output tile it.i.
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) {
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, r0 = it.i, m = threadIdx.x & 63, cg = threadIdx.x >> 6, r = r0 + m;
+  const int n = f.n, s = f.s;
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * mr;
-  const T *Wr = p.num + f.woff;
-  const T *Wi = Wr + (int64_t)n * f.wcols;
-  if (r0 < s) {
-    for (int e = threadIdx.x; e < 64 * nrhs; e += 256) {
-      const int mm = e % 64, j = e / 64;
-      if (r0 + mm < s) {
-        vr[r0 + mm + (int64_t)j * n] = Wr[r0 + mm + (int64_t)j * n];
-        vi[r0 + mm + (int64_t)j * n] = Wi[r0 + mm + (int64_t)j * n];
-      }
-    }
-  }
-  if (r0 + 64 <= s || r0 >= n) return;   // no update rows in this tile (uniform)
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
-    const int nj = min(8, nrhs - j0);
-    T ar[8], ai[8];
-    rows_dot(p, f, r0, 0, s, false, false, Wr, Wi, n, j0, nj, ar, ai, sr, si);
-    reduce4(ar, ai, rr, ri);
-    if (cg == 0 && r >= s && r < n)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nj) {
-          vr[r + (int64_t)(j0 + q) * n] -= ar[q];
-          vi[r + (int64_t)(j0 + q) * n] -= ai[q];
-        }
-  }
-}
-
-// t(columns c0..c0+64 of the fully-summed part) = z - L21^T x_R -> W scratch
-template <typename T>
-__global__ __launch_bounds__(256) void k_zbwd1(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T lr[64][NB + 1], li[64][NB + 1];
-  __shared__ T xr[64][17], xi[64][17];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, c0 = it.i, b = min(64, s - c0);
-  const int64_t mr = p.mr;
-  const T *vr = p.num + f.voff;
-  const T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
   T *Wr = p.num + f.woff;
   T *Wi = Wr + (int64_t)n * f.wcols;
-  const int c = threadIdx.x & 63, jg = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    if (s < n) col_dot(lr, li, xr, xi, fr, fi, vr, vi, n, c0, b, s, n, j0, nrhs, ar, ai);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + jg * 4 + q;
-      if (c < b && j < nrhs) {
-        const int64_t o = c0 + c + (int64_t)j * n;
-        Wr[o] = vr[o] - ar[q];
-        Wi[o] = vi[o] - ai[q];
-      }
-    }
-  }
-}
-
-// x_s(columns a0..a0+64, P basis) = Z^T t, written un-permuted into v
-template <typename T>
-__global__ __launch_bounds__(256) void k_zbwd2(KP<T> p, int64_t first, int nrhs) {
-  __shared__ T lr[64][NB + 1], li[64][NB + 1];
-  __shared__ T xr[64][17], xi[64][17];
-  const Item it = p.items[first + blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, a0 = it.i, b = min(64, s - a0);
-  const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
-  const T *Wr = p.num + f.woff;
-  const T *Wi = Wr + (int64_t)n * f.wcols;
+  const T *part = p.num + p.part;
   const int32_t *pm = p.perm + f.soff;
-  const int a = threadIdx.x & 63, jg = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    // rows below the diagonal tile: plain column dot with Z
-    if (a0 + 64 < s) col_dot(lr, li, xr, xi, fr, fi, Wr, Wi, n, a0, b, a0 + 64, s, j0, nrhs, ar, ai);
-    // diagonal tile: Z(c, a) for c >= a (unit diagonal)
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int mm = e % 64, j = e / 64;
-      T x0 = 0, x1 = 0;
-      if (mm < b && j0 + j < nrhs) {
-        const int64_t o = a0 + mm + (int64_t)(j0 + j) * n;
-        x0 = Wr[o];
-        x1 = Wi[o];
-      }
-      xr[mm][j] = x0;
-      xi[mm][j] = x1;
+  for (int e = threadIdx.x; e < 64 * nrhs; e += 256) {
+    const int o = e & 63, j = e >> 6, x = it.i + o;
+    if (x >= (M == 1 ? n : s)) continue;
+    T sr = 0, si = 0;
+    for (int k = it.k; k < it.k + it.j; ++k) {
+      const T *sl = part + (int64_t)k * 128 * mr + (int64_t)j * 64 + o;
+      sr += sl[0];
+      si += sl[64 * mr];
     }
-    __syncthreads();
-    if (a < b) {
-      for (int c = a; c < b; ++c) {
-        T zr = 1, zi = 0;
-        if (c > a) {
-          const int64_t o = (a0 + c) + (int64_t)(a0 + a) * n;
-          zr = fr[o];
-          zi = fi[o];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = jg * 4 + q;
-          ar[q] += zr * xr[c][j] - zi * xi[c][j];
-          ai[q] += zr * xi[c][j] + zi * xr[c][j];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = j0 + jg * 4 + q;
-        if (j < nrhs) {
-          const int64_t o = (a0 / NB) * NB + pm[a0 + a] + (int64_t)j * n;
-          vr[o] = ar[q];
-          vi[o] = ai[q];
-        }
-      }
+    const int64_t v = x + (int64_t)j * n;
+    if (M == 0) {
+      Wr[v] = sr; Wi[v] = si;
+      vr[v] = sr; vi[v] = si;
+    } else if (M == 1) {
+      vr[v] -= sr; vi[v] -= si;
+    } else if (M == 2) {
+      Wr[v] = vr[v] - sr; Wi[v] = vi[v] - si;
+    } else {
+      const int64_t d = (x / NB) * NB + pm[x] + (int64_t)j * n;
+      vr[d] = sr; vi[d] = si;
     }
   }
 }
@@ -2023,20 +1900,19 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
       case L_INVSYRK: hipLaunchKernelGGL(k_invsyrk<T>, g, b, 0, st, k, L.first); break;
       case S_FINIT: hipLaunchKernelGGL(k_finit<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_FDIAG: hipLaunchKernelGGL(k_fdiag<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_FUPD: hipLaunchKernelGGL(k_fupd<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_FFIN: hipLaunchKernelGGL(k_ffin<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_BINIT: hipLaunchKernelGGL(k_binit<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_BPART: hipLaunchKernelGGL(k_bpart<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_BDIAG: hipLaunchKernelGGL(k_bdiag<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_BFIN: hipLaunchKernelGGL(k_bfin<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_FFRONT: hipLaunchKernelGGL(k_ffront<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_BCOL: hipLaunchKernelGGL(k_bcol<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZFWD: hipLaunchKernelGGL(k_zfwd<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZFWD2: hipLaunchKernelGGL(k_zfwd2<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZBWD1: hipLaunchKernelGGL(k_zbwd1<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZBWD2: hipLaunchKernelGGL(k_zbwd2<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_BFRONT: hipLaunchKernelGGL(k_bfront<T>, g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP0: hipLaunchKernelGGL((k_zprod_n<T, 0>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZR0: hipLaunchKernelGGL((k_zred<T, 0>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP1: hipLaunchKernelGGL((k_zprod_n<T, 1>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZR1: hipLaunchKernelGGL((k_zred<T, 1>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP2: hipLaunchKernelGGL((k_zprod_t<T, 2>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZR2: hipLaunchKernelGGL((k_zred<T, 2>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP3: hipLaunchKernelGGL((k_zprod_t<T, 3>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZR3: hipLaunchKernelGGL((k_zred<T, 3>), g, b, 0, st, k, L.first, nrhs); break;
       default: return hipErrorInvalidValue;
     }
     if (timed) {

@@ -22,18 +22,22 @@ enum LaunchKind : int32_t {
   L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
   L_INVSYRK,    // X = P^T Z^T D^-1 Z P
   // solve
-  S_FINIT, S_FDIAG, S_FUPD, S_FFIN,
+  S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
+  S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)
   S_GEMV,       // interface: out = a*X*in + add
   S_MGATHER,    // d = sum_i B_i y_i - c
   S_HGATHER,    // h = B_Gamma^T lambda
-  S_BINIT, S_BPART, S_BDIAG, S_BFIN,
+  S_BINIT,      // update rows of the front vector from the global solution
+  S_BFIN,       // fully-summed rows of the front vector to the global solution
   S_FFRONT,     // whole-front forward substitution, one workgroup per front
   S_BFRONT,     // whole-front backward substitution, one workgroup per front
-  S_BCOL,       // pivot-tile right-hand side -= L21^T x (8 columns per workgroup)
-  S_ZFWD,       // y = Z P v_s for fronts carrying Z = L11^-1
-  S_ZFWD2,      // v_s = y, v_R -= L21 y
-  S_ZBWD1,      // t = z - L21^T x_R
-  S_ZBWD2,      // x_s = P^T Z^T t
+  // fronts carrying Z = L11^-1: split products (one partial slot per item,
+  // item = {front, slot, output tile, K chunk}) and their reductions
+  // (item = {front, first slot, output tile, slot count})
+  S_ZP0, S_ZR0, // y = Z P v_s;  v_s = y
+  S_ZP1, S_ZR1, // v_R -= L21 y
+  S_ZP2, S_ZR2, // t = z - L21^T x_R
+  S_ZP3, S_ZR3, // x_s = P^T Z^T t
 };
 
 struct Launch {
@@ -88,7 +92,7 @@ struct Plan {
   std::vector<Launch> solve_dom_bwd;   // Gamma scatter + interior backward
   std::vector<Item> gemv_items;        // interface GEMV items (one per 64-row tile)
   std::vector<double> dom_flops;       // factor flops per domain (fronts + interface inverse)
-  int64_t max_partials = 0;            // partial slots needed by S_BPART (per launch)
+  int64_t max_partials = 0;            // partial slots needed by the largest split product
 
   // ---- options / layout
   int32_t precision = 0;

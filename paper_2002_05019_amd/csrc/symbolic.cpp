@@ -606,7 +606,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       for (int v : h.rows) P.vars.push_back(v);
       d.vbase = P.dom_row[h.dom];
     }
+    // W: factorisation scratch (KBLK columns); fronts substituted through
+    // Z = L11^-1 also keep one intermediate column per right-hand side there
     d.wcols = std::max(KBLK, h.kind == FK_GAMMA ? 2 * NB : NB);
+    if (h.kind != FK_GAMMA && d.n > FUSE_N) d.wcols = std::max<int32_t>(d.wcols, P.max_rhs);
   }
   // children + reverse extend-add maps
   {
@@ -1084,56 +1087,73 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
 
   // solve: forward over a set of levels
   int64_t max_part = 0;
+  auto rows = [&](std::vector<Item> &v, int f, int lo, int hi) {
+    for (int r = lo; r < hi; r += 256) v.push_back({f, 0, r, 0});
+  };
+  // split product: 64-output tiles [o_lo, o_hi) x K chunks [k_lo(tile), k_hi(tile)),
+  // one partial slot per item, one reduction item per tile
+  auto split = [&](std::vector<Item> &prod, std::vector<Item> &red, int f, int o_lo, int o_hi, auto k_lo,
+                   auto k_hi) {
+    for (int i = o_lo; i < o_hi; i += 64) {
+      const int sbeg = (int)prod.size();
+      for (int c = k_lo(i); c < k_hi(i); c += ZKC) prod.push_back({f, (int)prod.size(), i, c});
+      red.push_back({f, sbeg, i, (int)prod.size() - sbeg});
+    }
+  };
   // Small fronts: one workgroup per front.  Fronts carrying Z = L11^-1:
-  // a few row/column-parallel triangular products per front.
+  // row-parallel gathers and split triangular / rectangular products.
   auto fwd = [&](std::vector<Launch> &seq, const std::vector<std::vector<int>> &levels, bool gamma_only_init) {
     for (auto &lv : levels) {
-      std::vector<Item> small, in, zf, zf2;
+      std::vector<Item> small, in, fin, p0, r0, p1, r1;
       for (int f : lv) {
         const FrontDev &d = P.fronts[f];
+        const int s = d.s, n = d.n;
         if (gamma_only_init) {
-          in.push_back({f, 0, 0, 0});
+          rows(in, f, 0, n);
           continue;
         }
         if (!zfront(f)) {
           small.push_back({f, 0, 0, 0});
           continue;
         }
-        in.push_back({f, 0, 0, 0});
-        for (int r = 0; r < d.s; r += 64) zf.push_back({f, 0, r, 0});
-        for (int r = 0; r < d.n; r += 64) zf2.push_back({f, 0, r, 0});
+        rows(in, f, 0, n);
+        rows(fin, f, 0, s);
+        split(p0, r0, f, 0, s, [](int) { return 0; }, [&](int i) { return std::min(i + 64, s); });
+        split(p1, r1, f, s, n, [](int) { return 0; }, [&](int) { return s; });
       }
+      max_part = std::max<int64_t>(max_part, std::max(p0.size(), p1.size()));
       push(seq, S_FFRONT, small);
       push(seq, S_FINIT, in);
-      push(seq, S_ZFWD, zf);
-      push(seq, S_ZFWD2, zf2);
-      if (!gamma_only_init) {
-        std::vector<Item> fin;
-        for (auto &it : in) fin.push_back(it);
-        push(seq, S_FFIN, fin);
-      }
+      push(seq, S_ZP0, p0);
+      push(seq, S_ZR0, r0);
+      push(seq, S_ZP1, p1);
+      push(seq, S_ZR1, r1);
+      push(seq, S_FFIN, fin);
     }
   };
   auto bwd = [&](std::vector<Launch> &seq, const std::vector<std::vector<int>> &levels) {
     for (auto it = levels.rbegin(); it != levels.rend(); ++it) {
-      std::vector<Item> small, in, zb1, zb2;
+      std::vector<Item> small, in, out, p2, r2, p3, r3;
       for (int f : *it) {
         const FrontDev &d = P.fronts[f];
+        const int s = d.s, n = d.n;
         if (!zfront(f)) {
           small.push_back({f, 0, 0, 0});
           continue;
         }
-        in.push_back({f, 0, 0, 0});
-        for (int c = 0; c < d.s; c += 64) {
-          zb1.push_back({f, 0, c, 0});
-          zb2.push_back({f, 0, c, 0});
-        }
+        rows(in, f, s, n);
+        rows(out, f, 0, s);
+        split(p2, r2, f, 0, s, [&](int) { return s; }, [&](int) { return n; });
+        split(p3, r3, f, 0, s, [](int i) { return i; }, [&](int) { return s; });
       }
+      max_part = std::max<int64_t>(max_part, std::max(p2.size(), p3.size()));
       push(seq, S_BFRONT, small);
       push(seq, S_BINIT, in);
-      push(seq, S_ZBWD1, zb1);
-      push(seq, S_ZBWD2, zb2);
-      push(seq, S_BFIN, in);
+      push(seq, S_ZP2, p2);
+      push(seq, S_ZR2, r2);
+      push(seq, S_ZP3, p3);
+      push(seq, S_ZR3, r3);
+      push(seq, S_BFIN, out);
     }
   };
   fwd(P.solve_dom_fwd, dom_levels, false);
@@ -1141,9 +1161,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   fwd(P.solve_aux, aux_levels, false);
   bwd(P.solve_aux, aux_levels);
   if (!gam.empty()) {
-    std::vector<Item> in;
-    for (int f : gam) in.push_back({f, 0, 0, 0});
-    push(P.solve_dom_bwd, S_BFIN, in);
+    std::vector<Item> out;
+    for (int f : gam) rows(out, f, 0, P.fronts[f].s);
+    push(P.solve_dom_bwd, S_BFIN, out);
   }
   bwd(P.solve_dom_bwd, dom_levels);
   for (int f : gam)
