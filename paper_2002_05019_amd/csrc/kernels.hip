@@ -296,36 +296,62 @@ __global__ __launch_bounds__(256) void k_auxg(KP<T> p, int64_t first) {
 // ---------------------------------------------------------------------------
 // pivot tile: restricted Bunch-Kaufman LDL^T of the NB x NB diagonal tile in
 // FP64, with L^-1 formed alongside (section II: pivot search confined to the
-// diagonal block).  The tile and L^-1 stay in registers, 2-D cyclic over a
-// 16 x 16 thread grid: thread (tr, tc) holds entries (tr + 16u, tc + 16v),
-// both triangles, in their original (physical) positions.  Interchanges are
-// never carried out on the data: the logical order is a permutation kept
-// per lane (lane a of every wave holds the physical index of position a),
-// and the not yet eliminated physical rows form a bit mask.  Per step only
-// the pivot column(s) and the matching rows of L^-1 pass through LDS; every
-// wave repeats the pivot search (identical result), so a step without a
-// rejected diagonal needs two barriers.
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+// diagonal block).
+//
+// The tile lives in registers, 2-D cyclic over the threads: thread (tr, tc)
+// holds entries (tr + 16u, tc + TC v), both triangles, in their original
+// (physical) positions.  Interchanges are never carried out on the data: the
+// logical order is a permutation kept per lane (lane a of every wave holds the
+// physical index of position a), and every thread keeps bits for its rows and
+// columns that are still active.  One register set M serves both matrices: an
+// active column holds the partially reduced tile A, an eliminated column holds
+// the corresponding column of L^-1 (the two never need updating at the same
+// entry; rows of eliminated pivots keep stale values in active columns, which
+// are never read).  The owners of the next pivot's column and row publish it
+// in LDS (masked and with the diagonal's reciprocal) at the end of each step;
+// every wave repeats the pivot test on it, and a step that keeps its diagonal
+// pivot needs one barrier.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false));
 }
-// a[w] for a block-uniform w in [0, 4) without dynamic register indexing
-__device__ __forceinline__ double pick4(double a0, double a1, double a2, double a3, int w) {
-  double r = a0;
-  r = w == 1 ? a1 : r;
-  r = w == 2 ? a2 : r;
-  r = w == 3 ? a3 : r;
-  return r;
+// maximum over the 64 lanes (DPP: quad swaps, half-row and row mirrors, then
+// row broadcasts 15 and 31 accumulate into lane 63), returned in every lane
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  v = fmax(v, dpp_f64<0x142, 0xA>(v));
+  v = fmax(v, dpp_f64<0x143, 0xC>(v));
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+// threads of the pivot-tile kernel
+constexpr int PANEL_NT = 512;
+// 1/x from the hardware reciprocal and one Newton step (a short dependency
+// chain; x = 0 gives a non-finite result, which the callers test for)
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_panel(KP<T> p, int64_t first) {
-  __shared__ double cjr[NB], cji[NB], c1r[NB], c1i[NB], ckr[NB], cki[NB];
-  __shared__ double yjr[NB], yji[NB], y1r[NB], y1i[NB];
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
+  // NT threads: rows tr + 16u (u < 4), columns tc + TC v (v < CV)
+  constexpr int TC = NT / 16, CV = NB / TC, NW = NT / 64;
+  static_assert(NT == 256 || NT == 512 || NT == 1024, "tile thread grid");
+  // A published pivot p: masked column (A(i, p) on active rows i != p, else
+  // 0), the update row z (A(c, p) on active columns, 1 at p, L^-1(p, c) on
+  // eliminated columns), the diagonal A(p, p) and its reciprocal.
+  // Buffers 0/1: the next 1 x 1 pivot (double-buffered); buffer 2: the
+  // candidate of a rejected diagonal.
+  __shared__ double cmr[3][NB], cmi[3][NB], zvr[3][NB], zvi[3][NB], dgs[3][4];
   __shared__ double dvr[NB], dvi[NB], dor[NB], doi[NB];
   __shared__ int pdl[NB], inv[NB];
-  __shared__ double red[4];
+  __shared__ double red[NW];
 
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -335,80 +361,150 @@ __global__ __launch_bounds__(256) void k_panel(KP<T> p, int64_t first) {
   T *fi = fr + (int64_t)n * n;
   constexpr double ALPHA = 0.6403882032022076;   // (1 + sqrt(17)) / 8
 
-  double ar[4][4], ai[4][4], yr[4][4], yi[4][4];
+  double mr[4][CV], mi[4][CV];
   double amax = 0;
+  unsigned rowbits = 0, colbits = 0;   // active rows u / columns v of this thread
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = tr + 16 * u, c = tc + 16 * v;
+    for (int v = 0; v < CV; ++v) {
+      const int i = tr + 16 * u, c = tc + TC * v;
       double xr = 0, xi = 0;
       if (i < b && c < b) {
         const int64_t o = (k + max(i, c)) + (int64_t)(k + min(i, c)) * n;
         xr = (double)fr[o];
         xi = (double)fi[o];
       }
-      ar[u][v] = xr;
-      ai[u][v] = xi;
+      mr[u][v] = xr;
+      mi[u][v] = xi;
       amax = fmax(amax, cabs1(xr, xi));
-      yr[u][v] = i == c ? 1.0 : 0.0;
-      yi[u][v] = 0.0;
+      if (i < b) rowbits |= 1u << u;
+      if (c < b) colbits |= 1u << v;
     }
   amax = wave_max(amax);
   if (lane == 0) red[tid >> 6] = amax;
-  __syncthreads();
-  const double tmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-  const double tau = tmax > 0 ? 1e-12 * tmax : 1.0;
 
-  // column col of the tile -> (dr, di)[physical row]; row row of L^-1 -> (er, ei)
-  auto put_col = [&](int col, double *dr, double *di) {
-    if (tc == (col & 15)) {
-      const int w = col >> 4;
+  // publishes pivot q (block-uniform) into buffer s; the register slot is
+  // picked by selects (no dynamic register indexing)
+  auto publish = [&](int q, int s) {
+    if (tc == q % TC) {
+      const int w = q / TC;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        dr[tr + 16 * u] = pick4(ar[u][0], ar[u][1], ar[u][2], ar[u][3], w);
-        di[tr + 16 * u] = pick4(ai[u][0], ai[u][1], ai[u][2], ai[u][3], w);
+        double xr = mr[u][0], xi = mi[u][0];
+#pragma unroll
+        for (int v = 1; v < CV; ++v) {
+          xr = w == v ? mr[u][v] : xr;
+          xi = w == v ? mi[u][v] : xi;
+        }
+        const int i = tr + 16 * u;
+        const bool act = ((rowbits >> u) & 1) && i != q;
+        cmr[s][i] = act ? xr : 0.0;
+        cmi[s][i] = act ? xi : 0.0;
+        if (act) {
+          zvr[s][i] = xr;
+          zvi[s][i] = xi;
+        }
+        if (i == q) {
+          const double rd = rcp_nr(fma(xr, xr, xi * xi));
+          dgs[s][0] = xr;
+          dgs[s][1] = xi;
+          dgs[s][2] = xr * rd;
+          dgs[s][3] = -xi * rd;
+        }
+      }
+    }
+    if (tr == (q & 15)) {
+      const int w = q >> 4;
+#pragma unroll
+      for (int v = 0; v < CV; ++v) {
+        double xr = mr[0][v], xi = mi[0][v];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+          xr = w == u ? mr[u][v] : xr;
+          xi = w == u ? mi[u][v] : xi;
+        }
+        const int c = tc + TC * v;
+        if (c == q) {
+          zvr[s][c] = 1.0;
+          zvi[s][c] = 0.0;
+        } else if (!((colbits >> v) & 1)) {
+          zvr[s][c] = xr;
+          zvi[s][c] = xi;
+        }
       }
     }
   };
-  auto put_yrow = [&](int row, double *er, double *ei) {
-    if (tr == (row & 15)) {
-      const int w = row >> 4;
+  // column q of M := 0 (it is about to receive -l, the new column of L^-1)
+  auto zero_col = [&](int q) {
+    if (tc == q % TC) {
+      const int w = q / TC;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        er[tc + 16 * v] = pick4(yr[0][v], yr[1][v], yr[2][v], yr[3][v], w);
-        ei[tc + 16 * v] = pick4(yi[0][v], yi[1][v], yi[2][v], yi[3][v], w);
-      }
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+          mr[u][v] = v == w ? 0.0 : mr[u][v];
+          mi[u][v] = v == w ? 0.0 : mi[u][v];
+        }
     }
+  };
+  auto retire = [&](int q) {
+    if (tr == (q & 15)) rowbits &= ~(1u << (q >> 4));
+    if (tc == q % TC) colbits &= ~(1u << (q / TC));
   };
 
-  int pv = lane;                                          // physical row at position `lane`
-  uint64_t alive = b == 64 ? ~0ull : ((1ull << b) - 1);   // physical rows not yet eliminated
+  int pv = lane;   // physical row at position `lane`
   int npert = 0;
-  int j = 0;
+  int j = 0, cur = 0;
+  publish(0, 0);
+  __syncthreads();
+  double tmax = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) tmax = fmax(tmax, red[w]);
+  const double tau = tmax > 0 ? 1e-12 * tmax : 1.0;
+
   while (j < b) {
-    int pj = __builtin_amdgcn_readlane(pv, j);
-    put_col(pj, cjr, cji);
-    put_yrow(pj, yjr, yji);
-    __syncthreads();
-    // pivot choice over positions j.. (physical rows pv), in every wave
-    const double absakk = cabs1(cjr[pj], cji[pj]);
+    // pivot pv[j] is published in buffer `cur`
+    const int pj = __builtin_amdgcn_readlane(pv, j);
+    int s = cur;   // buffer of the pivot actually used
+    // pivot test over positions j.. (physical rows pv), repeated by every
+    // wave; the column maximum is needed only if some entry rejects the
+    // diagonal.  LDS loads are unconditional and selected afterwards.
+    const double absakk = cabs1(dgs[cur][0], dgs[cur][1]);
+    // operands of a diagonal step, fetched ahead of the test (dependent
+    // FP64 latency, not issue, bounds this kernel)
+    double cr[4], ci[4], xzr[CV], xzi[CV];
+    double ir = dgs[cur][2], ii = dgs[cur][3];
+    bool zpiv = dgs[cur][0] == 0.0 && dgs[cur][1] == 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cr[u] = cmr[cur][tr + 16 * u];
+      ci[u] = cmi[cur][tr + 16 * u];
+    }
+#pragma unroll
+    for (int v = 0; v < CV; ++v) {
+      xzr[v] = zvr[cur][tc + TC * v];
+      xzi[v] = zvi[cur][tc + TC * v];
+    }
     const bool cand = lane > j && lane < b;
-    const double cv = cand ? cabs1(cjr[pv], cji[pv]) : -1.0;
-    const double colmax = wave_max(cv);
+    const double cvx = cabs1(cmr[cur][pv], cmi[cur][pv]);
+    const double cv = cand ? cvx : -1.0;
     int kind = 1, piv = j;
-    if (__builtin_amdgcn_readfirstlane(colmax > 0.0 && absakk < ALPHA * colmax)) {
+    if (__ballot(cand && absakk < ALPHA * cv)) {
+      const double colmax = wave_max(cv);
       // lowest position attaining the column maximum
       const int imax = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)__ballot(cand && cv == colmax)) - 1);
       const int pm = __builtin_amdgcn_readlane(pv, imax);
-      put_col(pm, ckr, cki);
+      publish(pm, 2);
       __syncthreads();
-      const double rv = (lane >= j && lane < b && lane != imax) ? cabs1(ckr[pv], cki[pv]) : -1.0;
+      // row imax of A over positions j.. = column pm on the active rows
+      const double rvx = cabs1(cmr[2][pv], cmi[2][pv]);
+      const double rv = (lane >= j && lane < b && lane != imax) ? rvx : -1.0;
       const double rowmax = wave_max(rv);
       if (absakk * rowmax >= ALPHA * colmax * colmax) {
         kind = 1;
         piv = j;
-      } else if (cabs1(ckr[pm], cki[pm]) >= ALPHA * rowmax) {
+      } else if (cabs1(dgs[2][0], dgs[2][1]) >= ALPHA * rowmax) {
         kind = 1;
         piv = imax;
       } else {
@@ -417,123 +513,131 @@ __global__ __launch_bounds__(256) void k_panel(KP<T> p, int64_t first) {
       }
       kind = __builtin_amdgcn_readfirstlane(kind);
       piv = __builtin_amdgcn_readfirstlane(piv);
-    }
-    const int q = kind == 1 ? j : j + 1;
-    if (piv != q) {
-      // interchange of positions q and piv: only the order changes
-      const int a0 = __builtin_amdgcn_readlane(pv, q), a1 = __builtin_amdgcn_readlane(pv, piv);
-      pv = lane == q ? a1 : (lane == piv ? a0 : pv);
-      if (kind == 1) {
-        // the new pivot column (old column piv) is in ck; L^-1 row again
-        pj = a1;
-        put_yrow(pj, yjr, yji);
-        __syncthreads();
+      const int q = kind == 1 ? j : j + 1;
+      if (piv != q) {
+        // interchange of positions q and piv: only the order changes
+        const int a0 = __builtin_amdgcn_readlane(pv, q), a1 = __builtin_amdgcn_readlane(pv, piv);
+        pv = lane == q ? a1 : (lane == piv ? a0 : pv);
+      }
+      if (kind == 1 && piv != q) {
+        // new pivot pm: its data is in buffer 2
+        s = 2;
+        ir = dgs[2][2];
+        ii = dgs[2][3];
+        zpiv = dgs[2][0] == 0.0 && dgs[2][1] == 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          cr[u] = cmr[2][tr + 16 * u];
+          ci[u] = cmi[2][tr + 16 * u];
+        }
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+          xzr[v] = zvr[2][tc + TC * v];
+          xzi[v] = zvi[2][tc + TC * v];
+        }
       }
     }
     if (kind == 1) {
-      // pivot column: cj, or ck after an interchange (it holds column pm)
-      const double *qr_ = piv != q ? ckr : cjr, *pi_ = piv != q ? cki : cji;
-      double dr = qr_[pj], di = pi_[pj];
-      if (dr == 0.0 && di == 0.0) {
-        dr = tau;
+      const int pp = s == 2 ? __builtin_amdgcn_readlane(pv, j) : pj;
+      if (zpiv) {
+        ir = 1.0 / tau;
+        ii = 0.0;
         ++npert;
       }
-      const double den = dr * dr + di * di;
-      const double ir = dr / den, ii = -di / den;
       if (tid == 0) {
         dvr[j] = ir; dvi[j] = ii; dor[j] = 0; doi[j] = 0; pdl[j] = 0;
       }
-      alive &= ~(1ull << pj);
-      // A(r, c) -= l(r) A(c, pj), L^-1(r, :) -= l(r) L^-1(pj, :) over alive r, c
-      double lr[4], li[4], wr[4], wi[4], er[4], ei[4];
+      // active rows r: M(r, c) -= A(r, pp) d^-1 z(c); the column pp becomes
+      // L^-1(:, pp) = -l.  Rows already eliminated (masked column 0) keep
+      // their L^-1 entries; their entries in active columns are stale and
+      // never read again.
+      double zr[CV], zi[CV];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = tr + 16 * u;
-        const bool ok = (alive >> i) & 1;
-        const double xr = ok ? qr_[i] : 0.0, xi = ok ? pi_[i] : 0.0;
-        lr[u] = xr * ir - xi * ii;
-        li[u] = xr * ii + xi * ir;
+      for (int v = 0; v < CV; ++v) {
+        zr[v] = xzr[v] * ir - xzi[v] * ii;
+        zi[v] = xzr[v] * ii + xzi[v] * ir;
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = tc + 16 * v;
-        const bool ok = (alive >> c) & 1;
-        wr[v] = ok ? qr_[c] : 0.0;
-        wi[v] = ok ? pi_[c] : 0.0;
-        er[v] = yjr[c];
-        ei[v] = yji[c];
-      }
+      zero_col(pp);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          ar[u][v] -= lr[u] * wr[v] - li[u] * wi[v];
-          ai[u][v] -= lr[u] * wi[v] + li[u] * wr[v];
-          yr[u][v] -= lr[u] * er[v] - li[u] * ei[v];
-          yi[u][v] -= lr[u] * ei[v] + li[u] * er[v];
+        for (int v = 0; v < CV; ++v) {
+          mr[u][v] = fma(-cr[u], zr[v], fma(ci[u], zi[v], mr[u][v]));
+          mi[u][v] = fma(-cr[u], zi[v], fma(-ci[u], zr[v], mi[u][v]));
         }
-      __syncthreads();
+      retire(pp);
       j += 1;
     } else {
+      // 2 x 2 pivot (pj, p1): pj in buffer cur, p1 (= pm) in buffer 2
       const int p1 = __builtin_amdgcn_readlane(pv, j + 1);
-      put_col(p1, c1r, c1i);
-      put_yrow(p1, y1r, y1i);
-      __syncthreads();
-      double ar_ = cjr[pj], ai_ = cji[pj], cr = cjr[p1], ci = cji[p1];
-      double er_ = c1r[p1], ei_ = c1i[p1];
-      double detr = (ar_ * er_ - ai_ * ei_) - (cr * cr - ci * ci);
-      double deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr * ci;
+      double ar_ = dgs[cur][0], ai_ = dgs[cur][1], cr_ = cmr[cur][p1], ci_ = cmi[cur][p1];
+      double er_ = dgs[2][0], ei_ = dgs[2][1];
+      double detr = (ar_ * er_ - ai_ * ei_) - (cr_ * cr_ - ci_ * ci_);
+      double deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr_ * ci_;
       if (detr == 0.0 && deti == 0.0) {
         ar_ += tau;
         er_ += tau;
-        detr = (ar_ * er_ - ai_ * ei_) - (cr * cr - ci * ci);
-        deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr * ci;
+        detr = (ar_ * er_ - ai_ * ei_) - (cr_ * cr_ - ci_ * ci_);
+        deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr_ * ci_;
         ++npert;
       }
-      const double den = detr * detr + deti * deti;
-      const double idr = detr / den, idi = -deti / den;   // 1/det
+      const double rden = rcp_nr(fma(detr, detr, deti * deti));
+      const double idr = detr * rden, idi = -deti * rden;   // 1/det
       // D^-1 = [[e, -c], [-c, a]] / det
       const double d00r = er_ * idr - ei_ * idi, d00i = er_ * idi + ei_ * idr;
       const double d11r = ar_ * idr - ai_ * idi, d11i = ar_ * idi + ai_ * idr;
-      const double d01r = -(cr * idr - ci * idi), d01i = -(cr * idi + ci * idr);
+      const double d01r = -(cr_ * idr - ci_ * idi), d01i = -(cr_ * idi + ci_ * idr);
       if (tid == 0) {
         dvr[j] = d00r; dvi[j] = d00i; dvr[j + 1] = d11r; dvi[j + 1] = d11i;
         dor[j] = d01r; doi[j] = d01i; dor[j + 1] = d01r; doi[j + 1] = d01i;
         pdl[j] = 1; pdl[j + 1] = -1;
       }
-      alive &= ~((1ull << pj) | (1ull << p1));
-      // [l0 l1](r) = [A(r, pj) A(r, p1)] D^-1;
-      // A(r, c) -= l0(r) A(c, pj) + l1(r) A(c, p1); L^-1(r, :) -= l0(r) L^-1(pj, :) + l1(r) L^-1(p1, :)
-      double l0r[4], l0i[4], l1r[4], l1i[4];
+      retire(pj);
+      retire(p1);
+      // active rows r: M(r, c) -= l0(r) z0(c) + l1(r) z1(c),
+      // [l0 l1](r) = [A(r, pj) A(r, p1)] D^-1; z0 (z1) is the update row of
+      // pj (p1) with the other pivot's entry 0
+      double l0r[4], l0i[4], l1r[4], l1i[4], z0r[CV], z0i[CV], z1r[CV], z1i[CV];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int i = tr + 16 * u;
-        const bool ok = (alive >> i) & 1;
-        const double a0r = ok ? cjr[i] : 0.0, a0i = ok ? cji[i] : 0.0;
-        const double a1r = ok ? c1r[i] : 0.0, a1i = ok ? c1i[i] : 0.0;
+        const bool ok = (rowbits >> u) & 1;
+        const double t0r = cmr[cur][tr + 16 * u], t0i = cmi[cur][tr + 16 * u];
+        const double t1r = cmr[2][tr + 16 * u], t1i = cmi[2][tr + 16 * u];
+        const double a0r = ok ? t0r : 0.0, a0i = ok ? t0i : 0.0;
+        const double a1r = ok ? t1r : 0.0, a1i = ok ? t1i : 0.0;
         l0r[u] = (a0r * d00r - a0i * d00i) + (a1r * d01r - a1i * d01i);
         l0i[u] = (a0r * d00i + a0i * d00r) + (a1r * d01i + a1i * d01r);
         l1r[u] = (a0r * d01r - a0i * d01i) + (a1r * d11r - a1i * d11i);
         l1i[u] = (a0r * d01i + a0i * d01r) + (a1r * d11i + a1i * d11r);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = tc + 16 * v;
-        const bool ok = (alive >> c) & 1;
-        const double w0r = ok ? cjr[c] : 0.0, w0i = ok ? cji[c] : 0.0;
-        const double w1r = ok ? c1r[c] : 0.0, w1i = ok ? c1i[c] : 0.0;
-        const double e0r = yjr[c], e0i = yji[c], e1r = y1r[c], e1i = y1i[c];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ar[u][v] -= (l0r[u] * w0r - l0i[u] * w0i) + (l1r[u] * w1r - l1i[u] * w1i);
-          ai[u][v] -= (l0r[u] * w0i + l0i[u] * w0r) + (l1r[u] * w1i + l1i[u] * w1r);
-          yr[u][v] -= (l0r[u] * e0r - l0i[u] * e0i) + (l1r[u] * e1r - l1i[u] * e1i);
-          yi[u][v] -= (l0r[u] * e0i + l0i[u] * e0r) + (l1r[u] * e1i + l1i[u] * e1r);
-        }
+      for (int v = 0; v < CV; ++v) {
+        const int c = tc + TC * v;
+        const double x0r = zvr[cur][c], x0i = zvi[cur][c], x1r = zvr[2][c], x1i = zvi[2][c];
+        z0r[v] = c == p1 ? 0.0 : x0r;
+        z0i[v] = c == p1 ? 0.0 : x0i;
+        z1r[v] = c == pj ? 0.0 : x1r;
+        z1i[v] = c == pj ? 0.0 : x1i;
       }
-      __syncthreads();
+      zero_col(pj);
+      zero_col(p1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+          double xr = mr[u][v], xi = mi[u][v];
+          xr = fma(-l0r[u], z0r[v], fma(l0i[u], z0i[v], xr));
+          xi = fma(-l0r[u], z0i[v], fma(-l0i[u], z0r[v], xi));
+          xr = fma(-l1r[u], z1r[v], fma(l1i[u], z1i[v], xr));
+          xi = fma(-l1r[u], z1i[v], fma(-l1i[u], z1r[v], xi));
+          mr[u][v] = xr;
+          mi[u][v] = xi;
+        }
       j += 2;
     }
+    if (j < b) publish(__builtin_amdgcn_readlane(pv, j), cur ^ 1);
+    cur ^= 1;
+    __syncthreads();
   }
   // L^-1 in the pivoted order into the strict lower triangle of the tile:
   // position (a, c) is physical (pv[a], pv[c])
@@ -542,14 +646,14 @@ __global__ __launch_bounds__(256) void k_panel(KP<T> p, int64_t first) {
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = tr + 16 * u, c = tc + 16 * v;
+    for (int v = 0; v < CV; ++v) {
+      const int i = tr + 16 * u, c = tc + TC * v;
       if (i < b && c < b) {
         const int a = inv[i], cc = inv[c];
         if (cc < a) {
           const int64_t o = (k + a) + (int64_t)(k + cc) * n;
-          fr[o] = (T)yr[u][v];
-          fi[o] = (T)yi[u][v];
+          fr[o] = (T)mr[u][v];
+          fi[o] = (T)mi[u][v];
         }
       }
     }
@@ -1893,7 +1997,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_ASM: hipLaunchKernelGGL(k_asm<T>, g, b, 0, st, k, L.first); break;
       case L_SCAT: hipLaunchKernelGGL(k_scat<T>, g, b, 0, st, k, L.first); break;
       case L_AUXG: hipLaunchKernelGGL(k_auxg<T>, g, b, 0, st, k, L.first); break;
-      case L_PANEL: hipLaunchKernelGGL(k_panel<T>, g, b, 0, st, k, L.first); break;
+      case L_PANEL: hipLaunchKernelGGL((k_panel<T, PANEL_NT>), g, dim3(PANEL_NT), 0, st, k, L.first); break;
       case L_TRSM: hipLaunchKernelGGL(k_trsm<T>, g, b, 0, st, k, L.first); break;
       case L_SYRK: hipLaunchKernelGGL(k_syrk<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
