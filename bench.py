@@ -55,11 +55,14 @@ def torn_residual(case, u, lam):
     return np.sqrt(r2) / np.linalg.norm(f, axis=0)
 
 
-def run_path(case, vals, f, prec, steps, warmup, timer_kernel, graph):
+def run_path(case, vals, f, prec, steps, warmup, graph, tune):
     import torch
     from paper_2002_05019_amd.binding import Solver
     nrhs = f.shape[1]
     s = Solver.from_case(case, precision=prec, max_rhs=max(8, nrhs), use_graph=graph).bind("cuda:0")
+    tiles = s.tune() if tune else None
+    if tiles:
+        log(f"[bench] {prec}: tuned Schur-update tiles per front-size bucket {tiles}")
     for _ in range(warmup):
         s.factor(vals)
         s.solve(f)
@@ -81,7 +84,7 @@ def run_path(case, vals, f, prec, steps, warmup, timer_kernel, graph):
     info = s.info()
     u, lam = s.solve(f, return_lam=True)
     torch.cuda.synchronize()
-    out = dict(solver=s, times=times, t_factor=tf, t_solve=ts, info=info, kt=kt,
+    out = dict(solver=s, times=times, t_factor=tf, t_solve=ts, info=info, kt=kt, tiles=tiles,
                u=u.cpu().numpy(), lam=lam.cpu().numpy(), status=s.last_status)
     return out
 
@@ -129,6 +132,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--graph", type=int, default=1, help="replay factor/solve from hipGraphs (1) or launch (0)")
+    ap.add_argument("--tune", type=int, default=1, help="autotune the Schur-update tiles before timing (1) or not (0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the solver is single-GPU); got --gpus {args.gpus}",
@@ -149,7 +153,7 @@ def main():
     res = {}
     paths = ["fp32_refine"] if args.no_fp64 else ["fp64", "fp32_refine"]
     for prec in paths:
-        res[prec] = run_path(case, vals, f, prec, args.steps, args.warmup, None, bool(args.graph))
+        res[prec] = run_path(case, vals, f, prec, args.steps, args.warmup, bool(args.graph), bool(args.tune))
         if prec == "fp32_refine":
             # kernel-level event timing of the Schur update in one extra
             # (untimed, plain-launch) factorisation of the same path
@@ -172,7 +176,8 @@ def main():
         "dtype": "complex64 fronts + fp64 refinement", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "domains": case.n_dom,
                    "unknowns": case.n_global, "multipliers": case.n_mult, "nrhs": nrhs,
-                   "precision": "fp32_refine", "refine_tol": 1e-9, "hipgraph": bool(args.graph)},
+                   "precision": "fp32_refine", "refine_tol": 1e-9, "hipgraph": bool(args.graph),
+                   "schur_tile_by_front_size": mx["tiles"]},
         "mixed": {"factor_ms": round(float(np.mean(mx["t_factor"])) * 1e3, 3),
                   "solve_ms": round(float(np.mean(mx["t_solve"])) * 1e3, 3),
                   "refine_iters": info["refine_iters"], "rel_resid": info["rel_resid"],
@@ -180,7 +185,7 @@ def main():
                   "n_perturbed": info["n_perturbed"]},
         "flops_per_step": flops,
         "roofline": None if achieved is None else {
-            "kernel": "schur_update (complex FP32 MFMA trailing update)", "bound": "mfma",
+            "kernel": "schur_update (complex FP32 MFMA trailing update, 64/128 tiles)", "bound": "mfma",
             "achieved": round(achieved, 3), "peak": PEAK["fp32_refine"], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK["fp32_refine"], 4), "traffic": None,
             "launches": kt["launches"], "avg_launch_us": round(kt["seconds"] / kt["launches"] * 1e6, 2)},

@@ -60,6 +60,10 @@ typedef enum {
 
 enum { DD_FP64 = 0, DD_FP32_REFINE = 1 };
 
+/* Front-size buckets of the Schur-update tile policy: fronts of size
+ * [0,512), [512,1024), [1024,2048), [2048,4096), [4096,...). */
+#define DD_TILE_BUCKETS 5
+
 /* Sparsity pattern of one domain matrix K_i (host memory).
  * Square n x n, CSR, 0-based, both triangles stored (structurally symmetric),
  * column indices strictly increasing within a row, every diagonal present. */
@@ -105,6 +109,10 @@ typedef struct {
                               hipGraphs on first use and replay them; 0: plain
                               launches.  Timed kernels always run plain.       */
     int32_t verbose;       /* print the symbolic summary to stderr              */
+    int32_t schur_tile[DD_TILE_BUCKETS];
+                           /* output tile edge of the trailing Schur update per
+                              front-size bucket: 64 or 128 (0 = library default:
+                              64 below 1024, 128 above); dd_tune measures it  */
 } dd_options;
 
 typedef struct {
@@ -199,6 +207,19 @@ enum {
 };
 dd_status dd_kernel_timer_start(dd_ctx ctx, int32_t kernel);
 dd_status dd_kernel_timer_read(dd_ctx ctx, double *seconds, int64_t *launches, double *flops);
+
+/* Tile autotuner (batching of uneven fronts, section II's many small dense
+ * operations): for every front-size bucket that has fronts, times the first
+ * outer block's Schur update of all its fronts with 64 x 64 and 128 x 128
+ * tiles on the bound workspace (a few launches each, events on hip_stream),
+ * keeps the faster one, re-plans the launch sequences with that policy and
+ * uploads them.  The workspace layout is unchanged.  schur_tile (may be NULL)
+ * receives the chosen edges, DD_TILE_BUCKETS entries (0 for empty buckets);
+ * pass them in dd_options.schur_tile to skip tuning next time.  Overwrites
+ * workspace contents: call it before dd_factor (a previous factorisation is
+ * discarded).  Synchronises hip_stream.
+ * Errors: DD_ERR_STATE (no workspace), DD_ERR_DEVICE. */
+dd_status dd_tune(dd_ctx ctx, int32_t *schur_tile, void *hip_stream);
 
 /* Releases the context (host state only; the workspace stays caller-owned). */
 void dd_destroy(dd_ctx ctx);

@@ -36,7 +36,7 @@ class dd_problem(C.Structure):
 class dd_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_maxit", C.c_int32),
                 ("max_rhs", C.c_int32), ("leaf_size", C.c_int32), ("use_graph", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("verbose", C.c_int32), ("schur_tile", C.c_int32 * 5)]
 
 
 class dd_info(C.Structure):
@@ -49,8 +49,9 @@ class dd_info(C.Structure):
 
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
            "dd_solve", "dd_get_info", "dd_get_interface_dofs", "dd_get_interface_inverse",
-           "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_destroy",
-           "dd_last_error"]
+           "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_tune",
+           "dd_destroy", "dd_last_error"]
+TILE_BUCKETS = 5   # front sizes [0,512) [512,1024) [1024,2048) [2048,4096) [4096,...)
 KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3}
 
 _lib = None
@@ -78,6 +79,7 @@ def load():
     lib.dd_get_domain_flops.argtypes = [vp, C.c_int32, _P(C.c_double)]
     lib.dd_kernel_timer_start.argtypes = [vp, C.c_int32]
     lib.dd_kernel_timer_read.argtypes = [vp, _P(C.c_double), _P(C.c_int64), _P(C.c_double)]
+    lib.dd_tune.argtypes = [vp, _P(C.c_int32), vp]
     lib.dd_destroy.argtypes = [vp]
     lib.dd_destroy.restype = None
     lib.dd_last_error.argtypes = []
@@ -115,7 +117,7 @@ class Solver:
 
     def __init__(self, rowptr, colind, n_mult, imap_ptr, imap_dof, imap_mult, imap_sign, xyz=None,
                  precision="fp64", max_rhs=64, leaf_size=48, refine_tol=1e-9, refine_maxit=20,
-                 use_graph=False, verbose=False):
+                 use_graph=False, verbose=False, schur_tile=None):
         lib = load()
         self._lib = lib
         nd = len(rowptr)
@@ -148,6 +150,10 @@ class Solver:
         opt.refine_maxit = int(refine_maxit)
         opt.verbose = int(bool(verbose))
         opt.use_graph = int(bool(use_graph))
+        if schur_tile is not None:
+            assert len(schur_tile) == TILE_BUCKETS
+            for b, t in enumerate(schur_tile):
+                opt.schur_tile[b] = int(t)
         self.precision = precision
         self.max_rhs = int(max_rhs)
         ctx = C.c_void_p()
@@ -241,6 +247,14 @@ class Solver:
         f = C.c_double()
         _check(self._lib.dd_get_domain_flops(self._ctx, dom, C.byref(f)))
         return f.value
+
+    def tune(self, stream=None):
+        """Autotune the Schur-update tile edge per front-size bucket on the
+        bound workspace (discards a previous factorisation).  Returns the
+        chosen edges (0 for empty buckets)."""
+        out = (C.c_int32 * TILE_BUCKETS)()
+        _check(self._lib.dd_tune(self._ctx, out, self._stream(stream)))
+        return [int(x) for x in out]
 
     def kernel_timer_start(self, kernel="schur_update"):
         _check(self._lib.dd_kernel_timer_start(self._ctx, -1 if kernel is None else KERNELS[kernel]))

@@ -2,10 +2,12 @@
 // the drivers of the numeric phases (see include/dd.h for the contract).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <chrono>
 #include <map>
 #include <utility>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,6 +29,16 @@ dd_status fail(dd_status s, const std::string &m) {
 struct dd_ctx_s {
   dd::Plan plan;
   dd_options opt;
+  // deep copy of the problem and the setup options, for re-planning (dd_tune)
+  dd::SetupOptions so;
+  std::vector<int32_t> n;
+  std::vector<std::vector<int64_t>> rowptr;
+  std::vector<std::vector<int32_t>> colind;
+  std::vector<int64_t> imap_ptr, imap_mult;
+  std::vector<int32_t> imap_dof;
+  std::vector<int8_t> imap_sign;
+  std::vector<float> xyz;
+  int64_t n_mult = 0;
   uint8_t *ws = nullptr;
   int64_t ws_bytes = 0;
   bool factored = false;
@@ -102,6 +114,7 @@ void dd_default_options(dd_options *o) {
   o->leaf_size = 48;
   o->use_graph = 0;
   o->verbose = 0;
+  for (int b = 0; b < DD_TILE_BUCKETS; ++b) o->schur_tile[b] = 0;
 }
 
 const char *dd_last_error(void) { return g_err.c_str(); }
@@ -121,6 +134,9 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
     if (o.refine_maxit < 0) return fail(DD_ERR_ARG, "refine_maxit must be >= 0");
     if (!(o.refine_tol > 0)) return fail(DD_ERR_ARG, "refine_tol must be > 0");
     if (o.use_graph != 0 && o.use_graph != 1) return fail(DD_ERR_ARG, "use_graph must be 0 or 1");
+    for (int b = 0; b < DD_TILE_BUCKETS; ++b)
+      if (o.schur_tile[b] != 0 && o.schur_tile[b] != 64 && o.schur_tile[b] != 128)
+        return fail(DD_ERR_ARG, "schur_tile entries must be 0, 64 or 128");
     if (prob->n_dom < 1 || !prob->dom) return fail(DD_ERR_ARG, "need at least one domain");
     auto t0 = std::chrono::steady_clock::now();
     dd::ProblemView pv;
@@ -145,12 +161,33 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
     so.max_rhs = o.max_rhs;
     so.leaf = o.leaf_size;
     so.verbose = o.verbose;
+    for (int b = 0; b < DD_TILE_BUCKETS; ++b) so.schur_tile[b] = o.schur_tile[b];
     dd_ctx_s *c = new dd_ctx_s;
     m = dd::build_plan(pv, so, c->plan);
     if (!m.empty()) {
       delete c;
       return fail(DD_ERR_PATTERN, m);
     }
+    c->so = so;
+    c->n_mult = prob->n_mult;
+    int64_t ntot = 0;
+    for (int i = 0; i < prob->n_dom; ++i) {
+      const dd_pattern &d = prob->dom[i];
+      c->n.push_back(d.n);
+      c->rowptr.emplace_back(d.rowptr, d.rowptr + d.n + 1);
+      c->colind.emplace_back(d.colind, d.colind + d.nnz);
+      ntot += d.n;
+    }
+    if (prob->imap_ptr) {
+      const int64_t ne = prob->imap_ptr[prob->n_dom];
+      c->imap_ptr.assign(prob->imap_ptr, prob->imap_ptr + prob->n_dom + 1);
+      if (ne > 0) {
+        c->imap_dof.assign(prob->imap_dof, prob->imap_dof + ne);
+        c->imap_mult.assign(prob->imap_mult, prob->imap_mult + ne);
+        c->imap_sign.assign(prob->imap_sign, prob->imap_sign + ne);
+      }
+    }
+    if (prob->dof_xyz) c->xyz.assign(prob->dof_xyz, prob->dof_xyz + 3 * ntot);
     c->opt = o;
     c->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = c;
@@ -379,6 +416,73 @@ dd_status dd_kernel_timer_read(dd_ctx c, double *seconds, int64_t *launches, dou
   *launches = c->tm.launches;
   *flops = c->tm.flops;
   return DD_OK;
+}
+
+dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  if (!c->ws) return fail(DD_ERR_STATE, "no workspace bound");
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    int choice[dd::TILE_BUCKETS];
+    for (int b = 0; b < dd::TILE_BUCKETS; ++b) {
+      choice[b] = 0;
+      const dd::Launch &l64 = c->plan.tune[b][0], &l128 = c->plan.tune[b][1];
+      if (l64.count == 0 || l128.count == 0) continue;
+      float best[2] = {1e30f, 1e30f};
+      for (int rep = 0; rep < 4; ++rep)
+        for (int v = 0; v < 2; ++v) {
+          HIPCHECK(hipEventRecord(e0, st));
+          HIPCHECK(dd::run_launch(c->plan, c->ws, v ? l128 : l64, st));
+          HIPCHECK(hipEventRecord(e1, st));
+          HIPCHECK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) best[v] = std::min(best[v], ms);   // first round warms up
+        }
+      choice[b] = best[1] < 0.97f * best[0] ? 128 : 64;
+      if (c->opt.verbose)
+        fprintf(stderr, "[dd] tile bucket %d: 64 -> %.3f ms, 128 -> %.3f ms: %d\n", b, best[0], best[1], choice[b]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // re-plan with the chosen policy (same workspace layout) and upload
+    dd::SetupOptions so = c->so;
+    for (int b = 0; b < dd::TILE_BUCKETS; ++b) {
+      if (choice[b]) so.schur_tile[b] = choice[b];
+      c->opt.schur_tile[b] = so.schur_tile[b];
+      if (schur_tile) schur_tile[b] = choice[b];
+    }
+    dd::ProblemView pv;
+    pv.n_dom = (int32_t)c->n.size();
+    pv.n_mult = c->n_mult;
+    for (size_t i = 0; i < c->n.size(); ++i) {
+      pv.n.push_back(c->n[i]);
+      pv.rowptr.push_back(c->rowptr[i].data());
+      pv.colind.push_back(c->colind[i].data());
+      pv.nnz.push_back((int64_t)c->colind[i].size());
+    }
+    pv.imap_ptr = c->imap_ptr.empty() ? nullptr : c->imap_ptr.data();
+    pv.imap_dof = c->imap_dof.empty() ? nullptr : c->imap_dof.data();
+    pv.imap_mult = c->imap_mult.empty() ? nullptr : c->imap_mult.data();
+    pv.imap_sign = c->imap_sign.empty() ? nullptr : c->imap_sign.data();
+    pv.xyz = c->xyz.empty() ? nullptr : c->xyz.data();
+    dd::Plan np;
+    std::string m = dd::build_plan(pv, so, np);
+    if (!m.empty()) return fail(DD_ERR_PATTERN, m);
+    if (np.b_total != c->plan.b_total || np.b_meta != c->plan.b_meta || np.meta.size() != c->plan.meta.size())
+      return fail(DD_ERR_STATE, "re-planned layout differs");
+    HIPCHECK(hipMemcpy(c->ws + np.b_meta, np.meta.data(), np.meta.size(), hipMemcpyHostToDevice));
+    c->plan = std::move(np);
+    c->so = so;
+    drop_graphs(c);
+    c->factored = false;
+    return DD_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "host allocation failed");
+  }
 }
 
 void dd_destroy(dd_ctx c) {

@@ -10,6 +10,8 @@ namespace dd {
 
 // numeric factorisation (enqueue only)
 hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm = nullptr);
+// one launch of the factorisation kernels (the tile tuner's measurements)
+hipError_t run_launch(const Plan &P, uint8_t *ws, const Launch &L, hipStream_t st);
 // torn right-hand sides (interleaved complex FP64, ld ldf) -> internal vector
 hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, hipStream_t st);
 // one DD solve of the internal right-hand side (with_c: constraint rhs in vc)

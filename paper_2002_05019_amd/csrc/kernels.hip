@@ -83,50 +83,79 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
 }
 
 constexpr int TK = 16;
-constexpr int LP = GT + 4;
 
-template <typename T>
+// Output tile of the MFMA GEMMs: BM x BN, WR x WC waves, each wave owning an
+// (XB*16) x (YB*16) block of 16 x 16 MFMA results.
+template <int BM_, int BN_, int WR_, int WC_>
+struct Tile {
+  static constexpr int BM = BM_, BN = BN_, WR = WR_, WC = WC_, NTH = 64 * WR_ * WC_;
+  static constexpr int XB = BM_ / (16 * WR_), YB = BN_ / (16 * WC_);
+  static constexpr int REPA = BM_ * TK / NTH, REPB = BN_ * TK / NTH;
+  // Position of element i of result block (x, y): row (the m index) and
+  // column (the c index) inside the tile.  The MFMA computes the transposed
+  // block (first operand from B, second from A) so that the 16 lanes of a
+  // result row run along m, the contiguous dimension of the column-major
+  // tiles.  Its result row index is 4*(lane/16) + i for the FP32 instruction
+  // and lane/16 + 4*i for the FP64 one; its column is lane%16.
+  __device__ static __forceinline__ int row(int x) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    return (w / WC_) * (XB * 16) + x * 16 + (lane & 15);
+  }
+  template <typename T>
+  __device__ static __forceinline__ int col(int y, int i) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int base = (w % WC_) * (YB * 16) + y * 16;
+    if (sizeof(T) == 8) return base + (lane >> 4) + 4 * i;
+    return base + (lane >> 4) * 4 + i;
+  }
+};
+using T64 = Tile<64, 64, 2, 2>;      // 256 threads, 2 x 2 blocks per wave
+using T128 = Tile<128, 128, 2, 4>;   // 512 threads, 4 x 2 blocks per wave
+
+template <typename T, class TL>
 struct GemmSmem {
-  T a[2][TK][LP];
-  T b[2][TK][LP];
+  T a[2][TK][TL::BM + 4];
+  T b[2][TK][TL::BN + 4];
 };
 
-// Accumulates a GT x GT complex tile P = sum_k A(m,k) B(c,k) over k in
+// Accumulates a BM x BN complex tile P = sum_k A(m,k) B(c,k) over k in
 // [kbeg, kend).  fa(m, k, re, im) / fb(c, k, re, im) return operand values
 // (and must leave zeros outside their valid range).  AK / BK select the
 // thread mapping of the loads: true when the operand is contiguous along k.
 // The next K chunk is fetched into registers while the current one is
-// multiplied.  Wave w owns rows 32*(w/2) + [0,32) and columns 32*(w%2) +
-// [0,32) as 2x2 MFMA 16x16 blocks.  The MFMA computes the transposed block
-// (first operand from B, second from A) so that the 16 lanes of a result row
-// run along m, the contiguous dimension of the column-major tiles; out_row /
-// out_col give the element positions.
-template <typename T, bool AK, bool BK, class FA, class FB>
-__device__ __forceinline__ void gemm_tile(GemmSmem<T> &sm, int kbeg, int kend, FA fa, FB fb,
-                                          typename V4<T>::t (&cr)[2][2], typename V4<T>::t (&ci)[2][2]) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+// multiplied.
+template <typename T, class TL, bool AK, bool BK, class FA, class FB>
+__device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int kend, FA fa, FB fb,
+                                          typename V4<T>::t (&cr)[TL::XB][TL::YB],
+                                          typename V4<T>::t (&ci)[TL::XB][TL::YB]) {
+  constexpr int NTH = TL::NTH, XB = TL::XB, YB = TL::YB, RA = TL::REPA, RB = TL::REPB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w / TL::WC, wc = w % TL::WC;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < YB; ++y) {
       cr[x][y] = typename V4<T>::t{0, 0, 0, 0};
       ci[x][y] = typename V4<T>::t{0, 0, 0, 0};
     }
-  T ra[2][4], rb[2][4];
+  // operand element `rep` of this thread: along k (contiguous) 16 threads
+  // cover one K chunk; otherwise BM (BN) threads cover one k
+  auto ma_ = [&](int rep) { return AK ? (tid >> 4) + (NTH / 16) * rep : tid % TL::BM; };
+  auto ka_ = [&](int rep) { return AK ? (tid & 15) : tid / TL::BM + (NTH / TL::BM) * rep; };
+  auto mb_ = [&](int rep) { return BK ? (tid >> 4) + (NTH / 16) * rep : tid % TL::BN; };
+  auto kb_ = [&](int rep) { return BK ? (tid & 15) : tid / TL::BN + (NTH / TL::BN) * rep; };
+  T ra[2][RA], rb[2][RB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int m = AK ? (tid >> 4) + 16 * rep : (tid & 63);
-      const int k = AK ? (tid & 15) : (tid >> 6) + 4 * rep;
+    for (int rep = 0; rep < RA; ++rep) {
+      const int m = ma_(rep), k = ka_(rep);
       T re = 0, im = 0;
       if (k0 + k < kend) fa(m, k0 + k, re, im);
       ra[0][rep] = re;
       ra[1][rep] = im;
     }
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int m = BK ? (tid >> 4) + 16 * rep : (tid & 63);
-      const int k = BK ? (tid & 15) : (tid >> 6) + 4 * rep;
+    for (int rep = 0; rep < RB; ++rep) {
+      const int m = mb_(rep), k = kb_(rep);
       T re = 0, im = 0;
       if (k0 + k < kend) fb(m, k0 + k, re, im);
       rb[0][rep] = re;
@@ -137,33 +166,35 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T> &sm, int kbeg, int kend, F
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
     __syncthreads();
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int ma = AK ? (tid >> 4) + 16 * rep : (tid & 63);
-      const int ka = AK ? (tid & 15) : (tid >> 6) + 4 * rep;
-      sm.a[0][ka][ma] = ra[0][rep];
-      sm.a[1][ka][ma] = ra[1][rep];
-      const int mb = BK ? (tid >> 4) + 16 * rep : (tid & 63);
-      const int kb = BK ? (tid & 15) : (tid >> 6) + 4 * rep;
-      sm.b[0][kb][mb] = rb[0][rep];
-      sm.b[1][kb][mb] = rb[1][rep];
+    for (int rep = 0; rep < RA; ++rep) {
+      sm.a[0][ka_(rep)][ma_(rep)] = ra[0][rep];
+      sm.a[1][ka_(rep)][ma_(rep)] = ra[1][rep];
+    }
+#pragma unroll
+    for (int rep = 0; rep < RB; ++rep) {
+      sm.b[0][kb_(rep)][mb_(rep)] = rb[0][rep];
+      sm.b[1][kb_(rep)][mb_(rep)] = rb[1][rep];
     }
     __syncthreads();
     if (k0 + TK < kend) fetch(k0 + TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      T ar[2], ai[2], br[2], bi[2];
+      T ar[XB], ai[XB], br[YB], bi[YB];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        ar[x] = sm.a[0][kr][wr * 32 + x * 16 + (lane & 15)];
-        ai[x] = sm.a[1][kr][wr * 32 + x * 16 + (lane & 15)];
-        br[x] = sm.b[0][kr][wc * 32 + x * 16 + (lane & 15)];
-        bi[x] = sm.b[1][kr][wc * 32 + x * 16 + (lane & 15)];
+      for (int x = 0; x < XB; ++x) {
+        ar[x] = sm.a[0][kr][wr * XB * 16 + x * 16 + (lane & 15)];
+        ai[x] = sm.a[1][kr][wr * XB * 16 + x * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < YB; ++y) {
+        br[y] = sm.b[0][kr][wc * YB * 16 + y * 16 + (lane & 15)];
+        bi[y] = sm.b[1][kr][wc * YB * 16 + y * 16 + (lane & 15)];
+      }
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+      for (int x = 0; x < XB; ++x)
+#pragma unroll
+        for (int y = 0; y < YB; ++y) {
           cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
           cr[x][y] = mfma16(-bi[y], ai[x], cr[x][y]);
           ci[x][y] = mfma16(bi[y], ar[x], ci[x][y]);
@@ -173,20 +204,10 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T> &sm, int kbeg, int kend, F
   }
 }
 
-// Position of element i of result block (x, y): row (the m index) and
-// column (the c index) inside the GT x GT tile.  The MFMA result row index is
-// 4*(lane/16) + i for the FP32 instruction and lane/16 + 4*i for the FP64 one;
-// its column is lane%16.
-__device__ __forceinline__ int out_row(int x) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  return (w >> 1) * 32 + x * 16 + (lane & 15);
-}
+// the 64 x 64 tile's output positions
+__device__ __forceinline__ int out_row(int x) { return T64::row(x); }
 template <typename T>
-__device__ __forceinline__ int out_col(int y, int i) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (sizeof(T) == 8) return (w & 1) * 32 + y * 16 + (lane >> 4) + 4 * i;
-  return (w & 1) * 32 + y * 16 + (lane >> 4) * 4 + i;
-}
+__device__ __forceinline__ int out_col(int y, int i) { return T64::col<T>(y, i); }
 
 __device__ __forceinline__ double cabs1(double r, double i) { return fabs(r) + fabs(i); }
 
@@ -673,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T> sm;
+  __shared__ GemmSmem<T, T64> sm;
   __shared__ T wr[GT][GT + 1], wi[GT][GT + 1];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -702,7 +723,7 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, false>(sm, 0, b, fa, fb, cr, ci);
+  gemm_tile<T, T64, false, false>(sm, 0, b, fa, fb, cr, ci);
   T *Wr = p.num + f.woff;
   T *Wi = Wr + (int64_t)n * f.wcols;
 #pragma unroll
@@ -744,9 +765,9 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
 // Trailing update (q0 >= block end): lower tiles of the trailing matrix,
 // kend = min(k + KBLK, s).  Column update (q0 < block end): the pivot tile
 // column starting at q0 receives the block's earlier tiles, kend = q0.
-template <typename T>
-__global__ __launch_bounds__(256) void k_syrk(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T> sm;
+template <typename T, class TL>
+__global__ __launch_bounds__(TL::NTH) void k_syrk(KP<T> p, int64_t first) {
+  __shared__ GemmSmem<T, TL> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int k = it.k, r0 = it.i, q0 = it.j, n = f.n;
@@ -774,16 +795,16 @@ __global__ __launch_bounds__(256) void k_syrk(KP<T> p, int64_t first) {
       im = Wi[o];
     }
   };
-  typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, false>(sm, k, kend, fa, fb, cr, ci);
+  typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
+  gemm_tile<T, TL, false, false>(sm, k, kend, fa, fb, cr, ci);
   const bool diag = (r0 == q0);
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < TL::XB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < TL::YB; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = out_row(x), c = out_col<T>(y, i);
+        const int m = TL::row(x), c = TL::template col<T>(y, i);
         const int r = r0 + m, q = q0 + c;
         if (r < n && q < qend && (!diag || m >= c)) {
           const int64_t o = r + (int64_t)q * n;
@@ -817,7 +838,7 @@ __device__ __forceinline__ void zval(const T *fr, const T *fi, int n, int r, int
 // Item (f, m0, r0, c0): output tile rows [r0, r0+64), columns [c0, c0+64).
 template <typename T>
 __global__ __launch_bounds__(256) void k_zrec1(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T> sm;
+  __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int m0 = it.k, r0 = it.i, c0 = it.j, n = f.n, s = f.s;
@@ -837,7 +858,7 @@ __global__ __launch_bounds__(256) void k_zrec1(KP<T> p, int64_t first) {
     zval(fr, fi, n, kk, c0 + c, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, true>(sm, c0, m0, fa, fb, cr, ci);
+  gemm_tile<T, T64, false, true>(sm, c0, m0, fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -855,7 +876,7 @@ __global__ __launch_bounds__(256) void k_zrec1(KP<T> p, int64_t first) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_zrec2(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T> sm;
+  __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int m0 = it.k, r0 = it.i, c0 = it.j, n = f.n, s = f.s;
@@ -873,7 +894,7 @@ __global__ __launch_bounds__(256) void k_zrec2(KP<T> p, int64_t first) {
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, false, false>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
+  gemm_tile<T, T64, false, false>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -892,7 +913,7 @@ __global__ __launch_bounds__(256) void k_zrec2(KP<T> p, int64_t first) {
 // X(P a, P c) = sum_r Z(r, a) (D^-1 Z)(r, c), lower tiles, written to both triangles
 template <typename T>
 __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T> sm;
+  __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int a0 = it.i, c0 = it.j, n = f.n;
@@ -926,7 +947,7 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
     im = (T)xi;
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, true, true>(sm, a0, n, fa, fb, cr, ci);
+  gemm_tile<T, T64, true, true>(sm, a0, n, fa, fb, cr, ci);
   T *Xr = p.num + f.xoff;
   T *Xi = Xr + (int64_t)n * n;
   const bool diag = (a0 == c0);
@@ -1986,7 +2007,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
                           KTimer *tm) {
   for (const Launch &L : seq) {
     dim3 g(L.count), b(256);
-    const bool timed = tm && tm->kind == L.kind && tm->used + 2 <= tm->cap;
+    const bool timed = tm && tm->kind == (L.kind == L_SYRK2 ? (int)L_SYRK : L.kind) && tm->used + 2 <= tm->cap;
     hipEvent_t *ev = timed ? (hipEvent_t *)tm->ev : nullptr;
     if (timed) {
       (void)hipEventRecord(ev[tm->used], st);
@@ -1999,7 +2020,8 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_AUXG: hipLaunchKernelGGL(k_auxg<T>, g, b, 0, st, k, L.first); break;
       case L_PANEL: hipLaunchKernelGGL((k_panel<T, PANEL_NT>), g, dim3(PANEL_NT), 0, st, k, L.first); break;
       case L_TRSM: hipLaunchKernelGGL(k_trsm<T>, g, b, 0, st, k, L.first); break;
-      case L_SYRK: hipLaunchKernelGGL(k_syrk<T>, g, b, 0, st, k, L.first); break;
+      case L_SYRK: hipLaunchKernelGGL((k_syrk<T, T64>), g, b, 0, st, k, L.first); break;
+      case L_SYRK2: hipLaunchKernelGGL((k_syrk<T, T128>), g, dim3(T128::NTH), 0, st, k, L.first); break;
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
       case L_INVSYRK: hipLaunchKernelGGL(k_invsyrk<T>, g, b, 0, st, k, L.first); break;
@@ -2058,6 +2080,12 @@ static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c
   e = run_seq<T>(P, k, P.solve_dom_bwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   return hipGetLastError();
+}
+
+hipError_t run_launch(const Plan &P, uint8_t *ws, const Launch &L, hipStream_t st) {
+  const std::vector<Launch> seq{L};
+  if (P.precision == 0) return run_seq<double>(P, make_kp<double>(P, ws, nullptr), seq, 0, st, nullptr);
+  return run_seq<float>(P, make_kp<float>(P, ws, nullptr), seq, 0, st, nullptr);
 }
 
 hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm) {

@@ -21,6 +21,7 @@ enum LaunchKind : int32_t {
   L_ZREC1,      // recursive inverse: T1 = P L21 Z11 (upper triangle)
   L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
   L_INVSYRK,    // X = P^T Z^T D^-1 Z P
+  L_SYRK2,      // trailing update on 128 x 128 tiles (512 threads)
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)
@@ -39,6 +40,11 @@ enum LaunchKind : int32_t {
   S_ZP2, S_ZR2, // t = z - L21^T x_R
   S_ZP3, S_ZR3, // x_s = P^T Z^T t
 };
+
+// front-size buckets of the Schur-update tile policy: n < 512, < 1024,
+// < 2048, < 4096, >= 4096
+constexpr int TILE_BUCKETS = 5;
+inline int tile_bucket(int n) { return n < 512 ? 0 : n < 1024 ? 1 : n < 2048 ? 2 : n < 4096 ? 3 : 4; }
 
 struct Launch {
   int32_t kind;
@@ -97,6 +103,10 @@ struct Plan {
   // ---- options / layout
   int32_t precision = 0;
   int32_t max_rhs = 64;
+  int32_t schur_tile[TILE_BUCKETS] = {64, 64, 64, 64, 64};   // resolved policy
+  // per bucket: the first outer block's trailing update of all fronts of the
+  // bucket with 64 (index 0) and 128 (index 1) tiles, for the tile tuner
+  Launch tune[TILE_BUCKETS][2] = {};
   size_t elem = 8;                     // sizeof(T)
   int64_t t_elems = 0;                 // T elements in the numeric region
   int64_t vf_off = 0, vx_off = 0, vd_off = 0, vl_off = 0, vc_off = 0, part_off = 0;
@@ -122,6 +132,7 @@ struct SetupOptions {
   int32_t leaf = 48;
   int32_t aux_leaf = 256;
   int32_t verbose = 0;
+  int32_t schur_tile[TILE_BUCKETS] = {0, 0, 0, 0, 0};   // 64 or 128; 0 = default
 };
 
 struct ProblemView {

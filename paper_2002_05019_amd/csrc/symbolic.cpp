@@ -374,6 +374,11 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.n_mult = p.n_mult;
   P.precision = o.precision;
   P.max_rhs = o.max_rhs;
+  // default Schur-update tiles: 64 below 1024, 128 from 1024 on
+  for (int bkt = 0; bkt < TILE_BUCKETS; ++bkt) {
+    const int t = o.schur_tile[bkt];
+    P.schur_tile[bkt] = t == 64 || t == 128 ? t : (bkt >= 2 ? 128 : 64);
+  }
   P.elem = o.precision == 0 ? sizeof(double) : sizeof(float);
   P.dom_n.assign(p.n.begin(), p.n.end());
   P.dom_row.resize(p.n_dom + 1);
@@ -895,6 +900,12 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         const double cnt = (it.i == it.j) ? rows * (rows + 1) / 2 : rows * cols;
         return 8.0 * K * cnt;
       }
+      case L_SYRK2: {   // trailing update on 128 x 128 tiles
+        const double K = std::min(it.k + KBLK, d.s) - it.k;
+        const double rows = std::min(128, n - it.i), cols = std::min(128, n - it.j);
+        const double cnt = (it.i == it.j) ? rows * (rows + 1) / 2 : rows * cols;
+        return 8.0 * K * cnt;
+      }
       case L_TRSM: {   // W = A21 P L^-T (triangular), L21 = W D^-1
         const double b = std::min(NB, d.s - it.k);
         const double rows = std::min(GT, n - it.i);
@@ -930,9 +941,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     L.p0 = p0;
     L.p1 = p1;
     L.flops = 0;
-    if (kind <= L_INVSYRK)
+    if (kind <= L_SYRK2)
       for (const Item &it : its) L.flops += item_flops(kind, it);
-    const bool gemm = kind == L_SYRK || kind == L_TRSM || kind == L_ZREC1 || kind == L_ZREC2 || kind == L_INVSYRK;
+    const bool gemm = kind == L_SYRK || kind == L_SYRK2 || kind == L_TRSM || kind == L_ZREC1 || kind == L_ZREC2 || kind == L_INVSYRK;
     if (gemm && its.size() >= 16) {
       // Workgroup b runs on XCD b % 8: give each XCD a contiguous run of the
       // item list (items sharing an operand panel are adjacent), so that
@@ -953,6 +964,14 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   // block every pivot tile first receives the updates of the block's earlier
   // tiles (column update), is factored (pivot tile + panel solve), and after
   // the block one trailing update with K = KBLK is applied.
+  int64_t item_pad = 0;
+  // lower tiles (edge ts) of the trailing matrix [kend, n) of front f, updated
+  // by the outer block starting at column o
+  auto trailing = [&](std::vector<Item> &out, int f, int o, int kend, int ts) {
+    const int nt = ntiles(P.fronts[f].n - kend, ts);
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = 0; tj <= ti; ++tj) out.push_back({f, o, kend + ti * ts, kend + tj * ts});
+  };
   auto factor_steps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
     int maxt = 0;
     for (int f : fs) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
@@ -974,17 +993,23 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         push(seq, L_PANEL, pan);
         push(seq, L_TRSM, trs);
       }
-      std::vector<Item> syr;
+      std::vector<Item> syr, syr2;
       for (int f : fs) {
         const FrontDev &d = P.fronts[f];
         const int o = ob * NB;
         if (o >= d.s) continue;
         const int kend = std::min(o + KBLK, d.s);
-        const int nt = ntiles(d.n - kend, GT);
-        for (int ti = 0; ti < nt; ++ti)
-          for (int tj = 0; tj <= ti; ++tj) syr.push_back({f, o, kend + ti * GT, kend + tj * GT});
+        const int ts = P.schur_tile[tile_bucket(d.n)];
+        trailing(ts == 128 ? syr2 : syr, f, o, kend, ts);
+        if (ts == 128) {
+          // keep the item array as long as with 64-tiles: the workspace
+          // layout must not depend on the tile policy
+          const int64_t a = ntiles(d.n - kend, 64), c = ntiles(d.n - kend, 128);
+          item_pad += a * (a + 1) / 2 - c * (c + 1) / 2;
+        }
       }
       push(seq, L_SYRK, syr);
+      push(seq, L_SYRK2, syr2);
     }
   };
   auto assemble = [&](std::vector<Launch> &seq, const std::vector<int> &fs, bool aux) {
@@ -1083,6 +1108,26 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     assemble(P.factor_seq, lv, true);
     factor_steps(P.factor_seq, lv);
     zsteps(P.factor_seq, zset(lv));
+  }
+  P.items.resize(P.items.size() + item_pad, Item{0, 0, 0, 0});
+  // tuner launches: first outer block's trailing update of every front of a
+  // bucket, with both tile edges
+  for (int bkt = 0; bkt < TILE_BUCKETS; ++bkt) {
+    std::vector<Item> t64, t128;
+    for (int f = 0; f < (int)P.fronts.size(); ++f) {
+      const FrontDev &d = P.fronts[f];
+      if (tile_bucket(d.n) != bkt || d.s == 0) continue;
+      const int kend = std::min(KBLK, d.s);
+      trailing(t64, f, 0, kend, 64);
+      trailing(t128, f, 0, kend, 128);
+    }
+    std::vector<Launch> tmp;
+    push(tmp, L_SYRK, t64);
+    push(tmp, L_SYRK2, t128);
+    if (tmp.size() == 2) {
+      P.tune[bkt][0] = tmp[0];
+      P.tune[bkt][1] = tmp[1];
+    }
   }
 
   // solve: forward over a set of levels

@@ -141,3 +141,34 @@ def test_repeat_runs_bitwise_identical():
     a = _solver(c).solve(_rhs(c)).cpu().numpy()
     b = _solver(c).solve(_rhs(c)).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_schur_tile_policy(tile):
+    """Every front's trailing update on one tile edge (128 also on fronts far
+    smaller than the tile, so ragged tiles everywhere)."""
+    c = cached_case("cube18u")
+    print(f"[parity] schur tile {tile} cube18u", flush=True)
+    s = _solver(c, schur_tile=[tile] * 5)
+    u = s.solve(_rhs(c))
+    torch.cuda.synchronize()
+    assert _colerr(u.cpu().numpy(), _ref("cube18u")["u"]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_tuned_tiles(precision):
+    """The tile tuner re-plans on the bound workspace; the factorisation after
+    it must still match the oracle."""
+    from paper_2002_05019_amd.binding import Solver
+    c = cached_case("cube24")
+    print(f"[parity] tuned tiles cube24 {precision}", flush=True)
+    s = Solver.from_case(c, precision=precision).bind(DEV)
+    tiles = s.tune()
+    assert len(tiles) == 5 and all(t in (0, 64, 128) for t in tiles)
+    assert any(t != 0 for t in tiles)
+    vals = torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV)
+    s.factor(vals)
+    u = s.solve(_rhs(c))
+    torch.cuda.synchronize()
+    tol = 1e-10 if precision == "fp64" else 1e-7
+    assert _colerr(u.cpu().numpy(), _ref("cube24")["u"]) < tol
