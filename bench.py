@@ -30,6 +30,8 @@ WORKLOADS = {
     "cube48": "48^3 Nedelec-hex curl-curl (318,096 unknowns), 4^3 domains of 12^3, eps_r U[1,4] tan-delta 0.02, "
               "k0 ~10 elements/wavelength, 8 complex-normal RHS",
     "cube24": "24^3 Nedelec-hex curl-curl, 3^3 domains of 8^3, 8 RHS (small check case)",
+    "cube64j": "64^3 Nedelec-hex curl-curl, nodes jittered +/-0.2h (762,048 unknowns), 216 domains from random "
+               "axis cuts of 6..14 elements, eps_r U[1,8] tan-delta 0.02, 64 complex-normal RHS",
 }
 
 

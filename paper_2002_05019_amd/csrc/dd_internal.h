@@ -15,6 +15,7 @@ constexpr int GT = 64;        // output tile edge of the MFMA GEMMs
 constexpr int KBLK = 256;     // outer block (columns per trailing update)
 constexpr int FUSE_N = 384;    // fronts up to this size are substituted by one workgroup
 constexpr int ZKC = 256;      // K chunk of the split substitution products
+constexpr int ZMMA_MIN = 8;   // above this many right-hand sides they run on MFMA
 
 enum FrontKind : int32_t { FK_INTERIOR = 0, FK_GAMMA = 1, FK_AUX = 2 };
 

@@ -82,7 +82,7 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int TK = 16;
+constexpr int TK = 16;   // K chunk per LDS stage
 
 // Output tile of the MFMA GEMMs: BM x BN, WR x WC waves, each wave owning an
 // (XB*16) x (YB*16) block of 16 x 16 MFMA results.
@@ -137,12 +137,12 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
       cr[x][y] = typename V4<T>::t{0, 0, 0, 0};
       ci[x][y] = typename V4<T>::t{0, 0, 0, 0};
     }
-  // operand element `rep` of this thread: along k (contiguous) 16 threads
+  // operand element `rep` of this thread: along k (contiguous) TK threads
   // cover one K chunk; otherwise BM (BN) threads cover one k
-  auto ma_ = [&](int rep) { return AK ? (tid >> 4) + (NTH / 16) * rep : tid % TL::BM; };
-  auto ka_ = [&](int rep) { return AK ? (tid & 15) : tid / TL::BM + (NTH / TL::BM) * rep; };
-  auto mb_ = [&](int rep) { return BK ? (tid >> 4) + (NTH / 16) * rep : tid % TL::BN; };
-  auto kb_ = [&](int rep) { return BK ? (tid & 15) : tid / TL::BN + (NTH / TL::BN) * rep; };
+  auto ma_ = [&](int rep) { return AK ? tid / TK + (NTH / TK) * rep : tid % TL::BM; };
+  auto ka_ = [&](int rep) { return AK ? tid % TK : tid / TL::BM + (NTH / TL::BM) * rep; };
+  auto mb_ = [&](int rep) { return BK ? tid / TK + (NTH / TK) * rep : tid % TL::BN; };
+  auto kb_ = [&](int rep) { return BK ? tid % TK : tid / TL::BN + (NTH / TL::BN) * rep; };
   T ra[2][RA], rb[2][RB];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -1581,6 +1581,109 @@ __global__ __launch_bounds__(256) void k_zprod_t(KP<T> p, int64_t first, int nrh
   }
 }
 
+// The same split products on the MFMA GEMM tile, for many right-hand sides
+// (64 at a time): the vector-unit kernels above re-read the front once per 8
+// columns.
+template <typename T>
+__device__ __forceinline__ void zslot_out(const typename V4<T>::t (&cr)[2][2], const typename V4<T>::t (&ci)[2][2],
+                                          T *slot, int64_t mr, int j0, int nrhs) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int o = out_row(x), j = j0 + out_col<T>(y, i);
+        if (j < nrhs) {
+          slot[(int64_t)j * 64 + o] = cr[x][y][i];
+          slot[64 * mr + (int64_t)j * 64 + o] = ci[x][y][i];
+        }
+      }
+}
+
+// M = 0, 1: A(o, k) is a row block of the front (contiguous along o)
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_zmma_n(KP<T> p, int64_t first, int nrhs) {
+  __shared__ GemmSmem<T, T64> sm;
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, i0 = it.i, c0 = it.j;
+  const int cend = min(c0 + ZKC, M == 0 ? min(s, i0 + 64) : s);
+  const int rlim = M == 0 ? s : n;
+  const int64_t mr = p.mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  const T *inr = M == 0 ? p.num + f.voff : p.num + f.woff;
+  const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
+  const int32_t *pm = p.perm + f.soff;
+  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
+  auto fa = [&](int m, int kk, T &re, T &im) {
+    const int r = i0 + m;
+    if (r < rlim) {
+      if (M != 0 || kk < r) {
+        const int64_t e = r + (int64_t)kk * n;
+        re = fr[e];
+        im = fi[e];
+      } else if (kk == r) {
+        re = 1;
+      }
+    }
+  };
+  for (int j0 = 0; j0 < nrhs; j0 += 64) {
+    auto fb = [&](int c, int kk, T &re, T &im) {
+      if (j0 + c < nrhs) {
+        const int src = M == 0 ? (kk / NB) * NB + pm[kk] : kk;
+        const int64_t e = src + (int64_t)(j0 + c) * n;
+        re = inr[e];
+        im = ini[e];
+      }
+    };
+    typename V4<T>::t cr[2][2], ci[2][2];
+    gemm_tile<T, T64, false, true>(sm, c0, cend, fa, fb, cr, ci);
+    zslot_out<T>(cr, ci, slot, mr, j0, nrhs);
+  }
+}
+
+// M = 2, 3: A(o, k) is a column block of the front read along its rows k
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs) {
+  __shared__ GemmSmem<T, T64> sm;
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, s = f.s, i0 = it.i, k0 = it.j;
+  const int kend = min(k0 + ZKC, M == 2 ? n : s);
+  const int64_t mr = p.mr;
+  const T *fr = p.num + f.off;
+  const T *fi = fr + (int64_t)n * n;
+  const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
+  const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
+  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
+  auto fa = [&](int m, int kk, T &re, T &im) {
+    const int col = i0 + m;
+    if (col < s) {
+      if (M == 2 || kk > col) {
+        const int64_t e = kk + (int64_t)col * n;
+        re = fr[e];
+        im = fi[e];
+      } else if (kk == col) {
+        re = 1;
+      }
+    }
+  };
+  for (int j0 = 0; j0 < nrhs; j0 += 64) {
+    auto fb = [&](int c, int kk, T &re, T &im) {
+      if (j0 + c < nrhs) {
+        const int64_t e = kk + (int64_t)(j0 + c) * n;
+        re = inr[e];
+        im = ini[e];
+      }
+    };
+    typename V4<T>::t cr[2][2], ci[2][2];
+    gemm_tile<T, T64, true, true>(sm, k0, kend, fa, fb, cr, ci);
+    zslot_out<T>(cr, ci, slot, mr, j0, nrhs);
+  }
+}
+
 // Reduction of the partial slots [it.k, it.k + it.j) of output tile it.i.
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) {
@@ -2031,13 +2134,25 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case S_BFIN: hipLaunchKernelGGL(k_bfin<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_FFRONT: hipLaunchKernelGGL(k_ffront<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_BFRONT: hipLaunchKernelGGL(k_bfront<T>, g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZP0: hipLaunchKernelGGL((k_zprod_n<T, 0>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP0:
+        if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_n<T, 0>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zprod_n<T, 0>), g, b, 0, st, k, L.first, nrhs);
+        break;
       case S_ZR0: hipLaunchKernelGGL((k_zred<T, 0>), g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZP1: hipLaunchKernelGGL((k_zprod_n<T, 1>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP1:
+        if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_n<T, 1>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zprod_n<T, 1>), g, b, 0, st, k, L.first, nrhs);
+        break;
       case S_ZR1: hipLaunchKernelGGL((k_zred<T, 1>), g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZP2: hipLaunchKernelGGL((k_zprod_t<T, 2>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP2:
+        if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_t<T, 2>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zprod_t<T, 2>), g, b, 0, st, k, L.first, nrhs);
+        break;
       case S_ZR2: hipLaunchKernelGGL((k_zred<T, 2>), g, b, 0, st, k, L.first, nrhs); break;
-      case S_ZP3: hipLaunchKernelGGL((k_zprod_t<T, 3>), g, b, 0, st, k, L.first, nrhs); break;
+      case S_ZP3:
+        if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_t<T, 3>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zprod_t<T, 3>), g, b, 0, st, k, L.first, nrhs);
+        break;
       case S_ZR3: hipLaunchKernelGGL((k_zred<T, 3>), g, b, 0, st, k, L.first, nrhs); break;
       default: return hipErrorInvalidValue;
     }

@@ -172,3 +172,24 @@ def test_tuned_tiles(precision):
     torch.cuda.synchronize()
     tol = 1e-10 if precision == "fp64" else 1e-7
     assert _colerr(u.cpu().numpy(), _ref("cube24")["u"]) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_many_rhs_on_matrix_cores(precision):
+    """70 right-hand sides in one block: the substitution products of the wide
+    fronts run on the MFMA tile (two 64-column passes)."""
+    c = cached_case("cube18u")
+    print(f"[parity] 70 rhs cube18u {precision}", flush=True)
+    rng = np.random.default_rng(7)
+    nr = 70
+    nt = sum(d.n for d in c.domains)
+    ft = (rng.standard_normal((nt, nr)) + 1j * rng.standard_normal((nt, nr))) / np.sqrt(2)
+    offs = np.cumsum([0] + [d.n for d in c.domains])
+    ref = oracle.serial_dd(c, F_rhs=[ft[offs[i]:offs[i + 1]] for i in range(c.n_dom)])
+    s = _solver(c, precision=precision, max_rhs=80)
+    u = s.solve(torch.from_numpy(ft).to(DEV))
+    torch.cuda.synchronize()
+    tol = 1e-10 if precision == "fp64" else 1e-7
+    assert _colerr(u.cpu().numpy(), ref["u"]) < tol
+    if precision == "fp32_refine":
+        assert s.info()["rel_resid"] <= 1e-9
