@@ -57,12 +57,13 @@ def torn_residual(case, u, lam):
     return np.sqrt(r2) / np.linalg.norm(f, axis=0)
 
 
-def run_path(case, vals, f, prec, steps, warmup, graph, tune):
+def run_path(case, vals, f, prec, steps, warmup, graph, tune, tiles=None, timed_events=False):
     import torch
     from paper_2002_05019_amd.binding import Solver
     nrhs = f.shape[1]
-    s = Solver.from_case(case, precision=prec, max_rhs=max(8, nrhs), use_graph=graph).bind("cuda:0")
-    tiles = s.tune() if tune else None
+    s = Solver.from_case(case, precision=prec, max_rhs=max(8, nrhs), use_graph=graph,
+                         schur_tile=tiles).bind("cuda:0")
+    tiles = s.tune() if tune and tiles is None else tiles
     if tiles:
         log(f"[bench] {prec}: tuned Schur-update tiles per front-size bucket {tiles}")
     for _ in range(warmup):
@@ -70,6 +71,10 @@ def run_path(case, vals, f, prec, steps, warmup, graph, tune):
         s.solve(f)
     torch.cuda.synchronize()
     times, tf, ts = [], [], []
+    if timed_events:
+        # HIP events around every Schur-update launch of the timed steps (the
+        # factorisation then runs as plain launches)
+        s.kernel_timer_start("schur_update")
     for _ in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -83,6 +88,9 @@ def run_path(case, vals, f, prec, steps, warmup, graph, tune):
         log(f"[bench] {prec} step {len(times)}: {times[-1] * 1e3:.1f} ms "
             f"(factor {tf[-1] * 1e3:.1f} ms, solve {ts[-1] * 1e3:.1f} ms)")
     kt = None
+    if timed_events:
+        kt = s.kernel_timer_read()
+        s.kernel_timer_start(None)
     info = s.info()
     u, lam = s.solve(f, return_lam=True)
     torch.cuda.synchronize()
@@ -99,6 +107,24 @@ def kernel_timing(solver, vals, kernel="schur_update"):
     kt = solver.kernel_timer_read()
     solver.kernel_timer_start(None)
     return kt
+
+
+def recorded_traffic(workload, tiles):
+    """HBM bytes per Schur-update launch from the committed rocprofv3 counter
+    record (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration), or
+    None when the kernels, the workload or the tile policy differ from the
+    measured ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"schur_update_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(os.path.join(ROOT, "paper_2002_05019_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()
+    if h != rec["kernels_hip_sha256"] or list(tiles or []) != rec["schur_tile_by_front_size"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(case, solver, budget_s=30.0):
@@ -135,11 +161,28 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--graph", type=int, default=1, help="replay factor/solve from hipGraphs (1) or launch (0)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the Schur-update tiles before timing (1) or not (0)")
+    ap.add_argument("--tiles", default=None,
+                    help="Schur-update tile edge per front-size bucket, e.g. 64,64,64,64,128 (implies --tune 0)")
+    ap.add_argument("--kernel-events", choices=["timed", "extra"], default="timed",
+                    help="time the Schur-update launches with HIP events inside the timed steps, or in one "
+                         "extra factorisation after them (then the timed steps replay graphs)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="only copy a buffer of this many MiB on the device and exit (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the solver is single-GPU); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib_mib:
+        import torch
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calib_mib} MiB")
+        return
+    tiles = [int(t) for t in args.tiles.split(",")] if args.tiles else None
     import numpy as np
     import torch
     from paper_2002_05019_amd.problem import make_case
@@ -155,8 +198,9 @@ def main():
     res = {}
     paths = ["fp32_refine"] if args.no_fp64 else ["fp64", "fp32_refine"]
     for prec in paths:
-        res[prec] = run_path(case, vals, f, prec, args.steps, args.warmup, bool(args.graph), bool(args.tune))
-        if prec == "fp32_refine":
+        res[prec] = run_path(case, vals, f, prec, args.steps, args.warmup, bool(args.graph), bool(args.tune), tiles,
+                             timed_events=(prec == "fp32_refine" and args.kernel_events == "timed"))
+        if prec == "fp32_refine" and args.kernel_events == "extra":
             # kernel-level event timing of the Schur update in one extra
             # (untimed, plain-launch) factorisation of the same path
             res[prec]["kt"] = kernel_timing(res[prec]["solver"], vals)
@@ -189,7 +233,8 @@ def main():
         "roofline": None if achieved is None else {
             "kernel": "schur_update (complex FP32 MFMA trailing update, 64/128 tiles)", "bound": "mfma",
             "achieved": round(achieved, 3), "peak": PEAK["fp32_refine"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK["fp32_refine"], 4), "traffic": None,
+            "frac": round(achieved / PEAK["fp32_refine"], 4),
+            "traffic": recorded_traffic(args.workload, mx["tiles"]),
             "launches": kt["launches"], "avg_launch_us": round(kt["seconds"] / kt["launches"] * 1e6, 2)},
     }
     if "fp64" in res:

@@ -442,7 +442,7 @@ dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
           HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
           if (rep > 0) best[v] = std::min(best[v], ms);   // first round warms up
         }
-      choice[b] = best[1] < 0.97f * best[0] ? 128 : 64;
+      choice[b] = best[1] < 0.9f * best[0] ? 128 : 64;   // 128 only when clearly faster
       if (c->opt.verbose)
         fprintf(stderr, "[dd] tile bucket %d: 64 -> %.3f ms, 128 -> %.3f ms: %d\n", b, best[0], best[1], choice[b]);
     }
