@@ -287,6 +287,10 @@ __global__ __launch_bounds__(256) void k_scat(KP<T> p, int64_t first) {
   }
 }
 
+// Auxiliary-front assembly: item (aux block pair, i0, j0) adds the 64 x 64
+// sub-block of sum_d s s' X_d(gb, ga) at rows pb + j, columns pa + i.  Lanes
+// run along j (contiguous front rows and interface positions); the four waves
+// take every fourth i.
 template <typename T>
 __global__ __launch_bounds__(256) void k_auxg(KP<T> p, int64_t first) {
   const Item it = p.items[first + blockIdx.x];
@@ -294,19 +298,29 @@ __global__ __launch_bounds__(256) void k_auxg(KP<T> p, int64_t first) {
   const FrontDev f = p.F[a.f];
   T *re = p.num + f.off;
   T *im = re + (int64_t)f.n * f.n;
-  const int total = a.na * a.nb;
-  for (int e = threadIdx.x; e < total; e += 256) {
-    const int j = e % a.nb, i = e / a.nb;
+  const int j = it.j + (threadIdx.x & 63), ig = threadIdx.x >> 6;
+  if (j >= a.nb) return;
+  int64_t gb[2];
+  int sb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    gb[t] = t < a.ndom ? p.gpos[a.gb[t] + j] : 0;
+    sb[t] = t < a.ndom ? p.gsign[a.gb[t] + j] : 0;
+  }
+  const int iend = min(it.i + 64, a.na);
+  for (int i = it.i + ig; i < iend; i += 4) {
     if (a.same && j < i) continue;
     T sr = 0, si = 0;
-    for (int t = 0; t < a.ndom; ++t) {
-      const int64_t ga = p.gpos[a.ga[t] + i], gb = p.gpos[a.gb[t] + j];
-      const int sg = p.gsign[a.ga[t] + i] * p.gsign[a.gb[t] + j];
-      const int64_t g = a.g[t];
-      const T *X = p.num + a.xoff[t];
-      const T xr = X[gb + ga * g], xi = X[g * g + gb + ga * g];
-      sr += sg > 0 ? xr : -xr;
-      si += sg > 0 ? xi : -xi;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t < a.ndom) {
+        const int64_t ga = p.gpos[a.ga[t] + i], g = a.g[t];
+        const int sg = p.gsign[a.ga[t] + i] * sb[t];
+        const T *X = p.num + a.xoff[t];
+        const T xr = X[gb[t] + ga * g], xi = X[g * g + gb[t] + ga * g];
+        sr += sg > 0 ? xr : -xr;
+        si += sg > 0 ? xi : -xi;
+      }
     }
     const int64_t o = (a.pb + j) + (int64_t)(a.pa + i) * f.n;
     re[o] += sr;

@@ -1023,8 +1023,14 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         for (int64_t b = 0; b < pr.second; b += 4096)
           sc.push_back({f, (int32_t)(pr.first + b), (int32_t)std::min<int64_t>(4096, pr.second - b), 0});
       } else {
+        // 64 x 64 sub-blocks of every block pair (lower part only on the diagonal)
         auto ar = arange[f];
-        for (int64_t b = 0; b < ar.second; ++b) ag.push_back({(int32_t)(ar.first + b), 0, 0, 0});
+        for (int64_t b = 0; b < ar.second; ++b) {
+          const AuxItem &a = P.aux_items[ar.first + b];
+          for (int i0 = 0; i0 < a.na; i0 += 64)
+            for (int j0 = 0; j0 < a.nb; j0 += 64)
+              if (!a.same || j0 + 64 > i0) ag.push_back({(int32_t)(ar.first + b), 0, i0, j0});
+        }
       }
     }
     push(seq, L_ASM, as);
