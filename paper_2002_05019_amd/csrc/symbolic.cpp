@@ -611,9 +611,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       for (int v : h.rows) P.vars.push_back(v);
       d.vbase = P.dom_row[h.dom];
     }
-    // W: factorisation scratch (KBLK columns); fronts substituted through
-    // Z = L11^-1 also keep one intermediate column per right-hand side there
-    d.wcols = std::max(KBLK, h.kind == FK_GAMMA ? 2 * NB : NB);
+    // W: factorisation scratch (one outer block of columns, at most KBLK);
+    // fronts substituted through Z = L11^-1 also keep one intermediate
+    // column per right-hand side there
+    d.wcols = std::max(NB, std::min(KBLK, (d.s + NB - 1) / NB * NB));
     if (h.kind != FK_GAMMA && d.n > FUSE_N) d.wcols = std::max<int32_t>(d.wcols, P.max_rhs);
   }
   // children + reverse extend-add maps
