@@ -55,6 +55,8 @@ struct dd_ctx_s {
   hipStream_t cap = nullptr;
   std::map<const void *, hipGraphExec_t> gfactor;
   std::map<std::pair<int, int>, hipGraphExec_t> gsolve;
+  // look-ahead of the factorisation: side stream and its two events
+  dd::SideStream side;
 };
 
 namespace {
@@ -216,6 +218,16 @@ dd_status dd_bind_workspace(dd_ctx c, void *dev, int64_t bytes) {
     c->events = true;
   }
   if (!c->cap) HIPCHECK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (!c->side.stream) {
+    hipStream_t s2;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+    c->side.stream = s2;
+    c->side.fork = e0;
+    c->side.join = e1;
+  }
   drop_graphs(c);
   c->ws = (uint8_t *)dev;
   c->ws_bytes = bytes;
@@ -239,12 +251,12 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
     auto it = c->gfactor.find(v);
     if (it == c->gfactor.end()) {
       hipGraphExec_t ge;
-      HIPCHECK(capture(c, [&](hipStream_t s) { return dd::factor(c->plan, c->ws, v, s, nullptr); }, &ge));
+      HIPCHECK(capture(c, [&](hipStream_t s) { return dd::factor(c->plan, c->ws, v, s, nullptr, &c->side); }, &ge));
       it = c->gfactor.emplace(v, ge).first;
     }
     HIPCHECK(hipGraphLaunch(it->second, st));
   } else {
-    HIPCHECK(dd::factor(c->plan, c->ws, v, st, c->tm.kind >= 0 ? &c->tm : nullptr));
+    HIPCHECK(dd::factor(c->plan, c->ws, v, st, c->tm.kind >= 0 ? &c->tm : nullptr, &c->side));
   }
   HIPCHECK(hipEventRecord(c->ev[1], st));
   c->fact_rec = true;
@@ -492,6 +504,11 @@ void dd_destroy(dd_ctx c) {
   for (auto &e : c->tev) (void)hipEventDestroy(e);
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->side.stream) {
+    (void)hipStreamDestroy((hipStream_t)c->side.stream);
+    (void)hipEventDestroy((hipEvent_t)c->side.fork);
+    (void)hipEventDestroy((hipEvent_t)c->side.join);
+  }
   delete c;
 }
 

@@ -33,7 +33,9 @@ struct FrontDev {
   int32_t nchild;
   int32_t kind;
   int32_t dom;     // owning domain (aux: -1)
-  int32_t wcols;   // columns of the W scratch (NB, or 2*NB for FK_GAMMA)
+  int32_t wcols;   // columns of one W scratch buffer
+  int64_t wstride; // fronts with more than one outer block: offset (T elements) of the
+                   // second W buffer, used by odd outer blocks; else 0
 };
 
 // Work item of one workgroup; the meaning of k, i, j depends on the kernel.

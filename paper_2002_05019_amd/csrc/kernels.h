@@ -8,8 +8,10 @@
 
 namespace dd {
 
-// numeric factorisation (enqueue only)
-hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm = nullptr);
+// numeric factorisation (enqueue only); with a side stream the trailing
+// updates' look-ahead part runs there, joined back before returning
+hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm = nullptr,
+                  const SideStream *side = nullptr);
 // one launch of the factorisation kernels (the tile tuner's measurements)
 hipError_t run_launch(const Plan &P, uint8_t *ws, const Launch &L, hipStream_t st);
 // torn right-hand sides (interleaved complex FP64, ld ldf) -> internal vector

@@ -738,7 +738,8 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
   };
   typename V4<T>::t cr[2][2], ci[2][2];
   gemm_tile<T, T64, false, false>(sm, 0, b, fa, fb, cr, ci);
-  T *Wr = p.num + f.woff;
+  // W buffer of the outer block starting at k - it.j
+  T *Wr = p.num + f.woff + (((k - it.j) / KBLK) & 1) * f.wstride;
   T *Wi = Wr + (int64_t)n * f.wcols;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -791,7 +792,7 @@ __global__ __launch_bounds__(TL::NTH) void k_syrk(KP<T> p, int64_t first) {
   const int qend = colupd ? min(q0 + NB, f.s) : n;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
-  const T *Wr = p.num + f.woff;
+  const T *Wr = p.num + f.woff + ((k / KBLK) & 1) * f.wstride;   // the outer block's W buffer
   const T *Wi = Wr + (int64_t)n * f.wcols;
   auto fa = [&](int m, int kk, T &re, T &im) {
     const int r = r0 + m;
@@ -2120,9 +2121,21 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
-static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launch> &seq, int nrhs, hipStream_t st,
-                          KTimer *tm) {
+static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launch> &seq, int nrhs, hipStream_t main,
+                          KTimer *tm, const SideStream *side = nullptr) {
+  const bool two = side && side->stream;
   for (const Launch &L : seq) {
+    if (L.kind == L_FORK || L.kind == L_JOIN) {
+      if (!two) continue;
+      hipEvent_t e = (hipEvent_t)(L.kind == L_FORK ? side->fork : side->join);
+      hipStream_t from = L.kind == L_FORK ? main : (hipStream_t)side->stream;
+      hipStream_t to = L.kind == L_FORK ? (hipStream_t)side->stream : main;
+      hipError_t r = hipEventRecord(e, from);
+      if (r == hipSuccess) r = hipStreamWaitEvent(to, e, 0);
+      if (r != hipSuccess) return r;
+      continue;
+    }
+    hipStream_t st = two && L.side ? (hipStream_t)side->stream : main;
     dim3 g(L.count), b(256);
     const bool timed = tm && tm->kind == (L.kind == L_SYRK2 ? (int)L_SYRK : L.kind) && tm->used + 2 <= tm->cap;
     hipEvent_t *ev = timed ? (hipEvent_t *)tm->ev : nullptr;
@@ -2184,10 +2197,11 @@ __global__ void k_zero_status(int *status) {
 }
 
 template <typename T>
-static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm) {
+static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm,
+                           const SideStream *side) {
   KP<T> k = make_kp<T>(P, ws, vals);
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, k.status);
-  return run_seq<T>(P, k, P.factor_seq, 0, st, tm);
+  return run_seq<T>(P, k, P.factor_seq, 0, st, tm, side);
 }
 
 template <typename T>
@@ -2217,8 +2231,8 @@ hipError_t run_launch(const Plan &P, uint8_t *ws, const Launch &L, hipStream_t s
   return run_seq<float>(P, make_kp<float>(P, ws, nullptr), seq, 0, st, nullptr);
 }
 
-hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm) {
-  return P.precision == 0 ? factor_t<double>(P, ws, vals, st, tm) : factor_t<float>(P, ws, vals, st, tm);
+hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, KTimer *tm, const SideStream *side) {
+  return P.precision == 0 ? factor_t<double>(P, ws, vals, st, tm, side) : factor_t<float>(P, ws, vals, st, tm, side);
 }
 
 hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, hipStream_t st) {

@@ -22,6 +22,8 @@ enum LaunchKind : int32_t {
   L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
   L_INVSYRK,    // X = P^T Z^T D^-1 Z P
   L_SYRK2,      // trailing update on 128 x 128 tiles (512 threads)
+  L_FORK,       // side stream waits for the main stream (no kernel)
+  L_JOIN,       // main stream waits for the side stream (no kernel)
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)
@@ -52,6 +54,15 @@ struct Launch {
   int64_t first;     // first item in the kind's item array
   int32_t p0, p1;    // kind-specific
   double flops;      // algorithmic real flops of the launch (complex FMA = 8)
+  int32_t side = 0;  // 1: enqueued on the side stream (look-ahead of the factorisation)
+};
+
+// Side stream and the two events of the factorisation's look-ahead (owned by
+// the caller; null stream = everything on the main stream).
+struct SideStream {
+  void *stream = nullptr;   // hipStream_t
+  void *fork = nullptr;     // hipEvent_t
+  void *join = nullptr;     // hipEvent_t
 };
 
 // Optional per-kernel event timer (diagnostics): brackets every launch of

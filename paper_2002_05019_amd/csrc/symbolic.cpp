@@ -811,7 +811,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   for (int f = 0; f < nf; ++f) {
     FrontDev &d = P.fronts[f];
     d.woff = at;
-    at = align(at + 2 * (int64_t)d.n * d.wcols);
+    const int64_t wbuf = align(2 * (int64_t)d.n * d.wcols);
+    d.wstride = d.s > KBLK ? wbuf : 0;   // second buffer for odd outer blocks
+    at = align(at + wbuf + d.wstride);
   }
   for (int f = 0; f < nf; ++f) {
     FrontDev &d = P.fronts[f];
@@ -973,10 +975,32 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     for (int ti = 0; ti < nt; ++ti)
       for (int tj = 0; tj <= ti; ++tj) out.push_back({f, o, kend + ti * ts, kend + tj * ts});
   };
+  // stream synchronisation points of the look-ahead (no kernel)
+  auto sync = [&](std::vector<Launch> &seq, int kind) {
+    Launch L{};
+    L.kind = kind;
+    L.count = 0;
+    L.first = 0;
+    L.flops = 0;
+    seq.push_back(L);
+  };
+  auto push_side = [&](std::vector<Launch> &seq, int kind, const std::vector<Item> &its) {
+    const size_t before = seq.size();
+    push(seq, kind, its);
+    if (seq.size() > before) seq.back().side = 1;
+  };
+  // Outer blocks of KBLK columns.  Inside a block each pivot tile gets the
+  // block's earlier tiles (column update), its pivot-tile factorisation and
+  // its panel solve.  The block's trailing update is split: the strip of the
+  // next block's columns runs on the main stream, the rest on the side
+  // stream, overlapping the next block's (latency-bound) pivot chain; the
+  // main stream waits for it before the next trailing update.  Odd outer
+  // blocks use the second W buffer.
   auto factor_steps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
     int maxt = 0;
     for (int f : fs) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
     const int G = KBLK / NB;
+    bool pending = false;
     for (int ob = 0; ob < maxt; ob += G) {
       for (int t = ob; t < ob + G && t < maxt; ++t) {
         std::vector<Item> upd, pan, trs;
@@ -994,14 +1018,16 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         push(seq, L_PANEL, pan);
         push(seq, L_TRSM, trs);
       }
-      std::vector<Item> syr, syr2;
+      std::vector<Item> syr[2], syr2[2];   // [0]: next block's strip, [1]: rest
       for (int f : fs) {
         const FrontDev &d = P.fronts[f];
         const int o = ob * NB;
         if (o >= d.s) continue;
         const int kend = std::min(o + KBLK, d.s);
         const int ts = P.schur_tile[tile_bucket(d.n)];
-        trailing(ts == 128 ? syr2 : syr, f, o, kend, ts);
+        std::vector<Item> all;
+        trailing(all, f, o, kend, ts);
+        for (const Item &it : all) (ts == 128 ? syr2 : syr)[it.j < kend + KBLK ? 0 : 1].push_back(it);
         if (ts == 128) {
           // keep the item array as long as with 64-tiles: the workspace
           // layout must not depend on the tile policy
@@ -1009,9 +1035,17 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
           item_pad += a * (a + 1) / 2 - c * (c + 1) / 2;
         }
       }
-      push(seq, L_SYRK, syr);
-      push(seq, L_SYRK2, syr2);
+      if (pending) sync(seq, L_JOIN);
+      push(seq, L_SYRK, syr[0]);
+      push(seq, L_SYRK2, syr2[0]);
+      pending = !syr[1].empty() || !syr2[1].empty();
+      if (pending) {
+        sync(seq, L_FORK);
+        push_side(seq, L_SYRK, syr[1]);
+        push_side(seq, L_SYRK2, syr2[1]);
+      }
     }
+    if (pending) sync(seq, L_JOIN);
   };
   auto assemble = [&](std::vector<Launch> &seq, const std::vector<int> &fs, bool aux) {
     std::vector<Item> as, sc, ag;
