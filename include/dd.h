@@ -113,6 +113,12 @@ typedef struct {
                            /* output tile edge of the trailing Schur update per
                               front-size bucket: 64 or 128 (0 = library default:
                               64 below 1024, 128 above); dd_tune measures it  */
+    int32_t verify_schedule;
+                           /* 1: dd_setup (and dd_tune's re-plan) also checks
+                              on the host that the factorisation's launches on
+                              its side streams never touch data that an
+                              unordered launch writes (DD_ERR_STATE if they
+                              do); costs host time, for tests               */
 } dd_options;
 
 typedef struct {

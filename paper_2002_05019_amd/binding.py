@@ -36,7 +36,8 @@ class dd_problem(C.Structure):
 class dd_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_maxit", C.c_int32),
                 ("max_rhs", C.c_int32), ("leaf_size", C.c_int32), ("use_graph", C.c_int32),
-                ("verbose", C.c_int32), ("schur_tile", C.c_int32 * 5)]
+                ("verbose", C.c_int32), ("schur_tile", C.c_int32 * 5),
+                ("verify_schedule", C.c_int32)]
 
 
 class dd_info(C.Structure):
@@ -117,7 +118,7 @@ class Solver:
 
     def __init__(self, rowptr, colind, n_mult, imap_ptr, imap_dof, imap_mult, imap_sign, xyz=None,
                  precision="fp64", max_rhs=64, leaf_size=48, refine_tol=1e-9, refine_maxit=20,
-                 use_graph=False, verbose=False, schur_tile=None):
+                 use_graph=False, verbose=False, schur_tile=None, verify_schedule=False):
         lib = load()
         self._lib = lib
         nd = len(rowptr)
@@ -150,6 +151,7 @@ class Solver:
         opt.refine_maxit = int(refine_maxit)
         opt.verbose = int(bool(verbose))
         opt.use_graph = int(bool(use_graph))
+        opt.verify_schedule = int(bool(verify_schedule))
         if schur_tile is not None:
             assert len(schur_tile) == TILE_BUCKETS
             for b, t in enumerate(schur_tile):

@@ -117,6 +117,7 @@ void dd_default_options(dd_options *o) {
   o->use_graph = 0;
   o->verbose = 0;
   for (int b = 0; b < DD_TILE_BUCKETS; ++b) o->schur_tile[b] = 0;
+  o->verify_schedule = 0;
 }
 
 const char *dd_last_error(void) { return g_err.c_str(); }
@@ -164,11 +165,19 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
     so.leaf = o.leaf_size;
     so.verbose = o.verbose;
     for (int b = 0; b < DD_TILE_BUCKETS; ++b) so.schur_tile[b] = o.schur_tile[b];
+    so.verify = o.verify_schedule;
     dd_ctx_s *c = new dd_ctx_s;
     m = dd::build_plan(pv, so, c->plan);
     if (!m.empty()) {
       delete c;
       return fail(DD_ERR_PATTERN, m);
+    }
+    if (so.verify) {
+      m = dd::check_schedule(c->plan, c->plan.factor_seq);
+      if (!m.empty()) {
+        delete c;
+        return fail(DD_ERR_STATE, "stream schedule check: " + m);
+      }
     }
     c->so = so;
     c->n_mult = prob->n_mult;
@@ -241,11 +250,8 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
   if (!vals && c->plan.nnz_total > 0) return fail(DD_ERR_ARG, "vals is null");
   hipStream_t st = (hipStream_t)stream;
   const void *v = vals;
-  if (c->plan.precision != 0) {
-    // FP64 copy of the operator for the refinement residuals
-    HIPCHECK(hipMemcpyAsync(c->ws + c->plan.b_vals, vals, c->plan.nnz_total * 16, hipMemcpyDeviceToDevice, st));
-    v = c->ws + c->plan.b_vals;
-  }
+  // FP64 copy of the operator for the refinement residuals
+  if (c->plan.precision != 0) HIPCHECK(dd::operator_copy(c->plan, c->ws, vals, st));
   HIPCHECK(hipEventRecord(c->ev[0], st));
   if (c->opt.use_graph && c->tm.kind < 0) {
     auto it = c->gfactor.find(v);
@@ -484,6 +490,10 @@ dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
     dd::Plan np;
     std::string m = dd::build_plan(pv, so, np);
     if (!m.empty()) return fail(DD_ERR_PATTERN, m);
+    if (so.verify) {
+      m = dd::check_schedule(np, np.factor_seq);
+      if (!m.empty()) return fail(DD_ERR_STATE, "stream schedule check: " + m);
+    }
     if (np.b_total != c->plan.b_total || np.b_meta != c->plan.b_meta || np.meta.size() != c->plan.meta.size())
       return fail(DD_ERR_STATE, "re-planned layout differs");
     HIPCHECK(hipMemcpy(c->ws + np.b_meta, np.meta.data(), np.meta.size(), hipMemcpyHostToDevice));
@@ -504,11 +514,9 @@ void dd_destroy(dd_ctx c) {
   for (auto &e : c->tev) (void)hipEventDestroy(e);
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
-  if (c->side.stream) {
-    (void)hipStreamDestroy((hipStream_t)c->side.stream);
-    (void)hipEventDestroy((hipEvent_t)c->side.fork);
-    (void)hipEventDestroy((hipEvent_t)c->side.join);
-  }
+  if (c->side.stream) (void)hipStreamDestroy((hipStream_t)c->side.stream);
+  for (void *e : {c->side.fork, c->side.join})
+    if (e) (void)hipEventDestroy((hipEvent_t)e);
   delete c;
 }
 

@@ -23,6 +23,9 @@ hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, 
                    hipStream_t st);
 hipError_t interface_inverse_out(const Plan &P, uint8_t *ws, int front, void *out, hipStream_t st);
 // FP64 iterative refinement around the FP32 factorisation
+// FP64 copy of the operator values (caller's CSR order) into the workspace's
+// SELL-64 layout, read by the refinement residual
+hipError_t operator_copy(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st);
 hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st);
 hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st);
 hipError_t refine_resid(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, bool fnorm,

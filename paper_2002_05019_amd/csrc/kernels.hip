@@ -45,7 +45,8 @@ struct KP {
   const int32_t *hsign;
   const int32_t *rowgam;
   const int64_t *csrp;
-  const int32_t *csrc;
+  const int64_t *sellp;
+  const int32_t *sellc;
   const Item *gemv;
   T *num;
   cd *dinv;
@@ -1523,13 +1524,13 @@ __global__ __launch_bounds__(256) void k_zprod_n(KP<T> p, int64_t first, int nrh
     if (live) {
 #pragma unroll 4
       for (int c = c0 + g; c < cend; c += 4) {
-        T zr = 0, zi = 0;
-        if (M != 0 || c < r) {
-          const int64_t e = r + (int64_t)c * n;
-          zr = fr[e];
-          zi = fi[e];
-        } else if (c == r) {
-          zr = 1;
+        // unconditional loads (the address is inside the square front), so
+        // that the unrolled iterations keep several loads in flight
+        const int64_t e = r + (int64_t)c * n;
+        T zr = fr[e], zi = fi[e];
+        if (M == 0 && c >= r) {
+          zr = c == r ? T(1) : T(0);
+          zi = 0;
         }
         zacc(&xs[(c - c0) * 16], zr, zi, ar, ai);
       }
@@ -1562,17 +1563,23 @@ __global__ __launch_bounds__(256) void k_zprod_t(KP<T> p, int64_t first, int nrh
     for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
     for (int rb = k0; rb < kend; rb += 64) {
       __syncthreads();
-      for (int e = tid; e < 64 * 64; e += 256) {
-        const int rr = e & 63, cc = e >> 6, row = rb + rr, col = i0 + cc;
-        T vr = 0, vi = 0;
-        if (row < kend && col < s) {
-          if (M == 2 || row > col) {
-            const int64_t x = row + (int64_t)col * n;
-            vr = fr[x];
-            vi = fi[x];
-          } else if (row == col) {
-            vr = 1;
-          }
+      // clamped, unconditional loads: all 32 of a thread can be in flight
+      T tv[2][16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, rr = e & 63, cc = e >> 6;
+        const int row = min(rb + rr, kend - 1), col = min(i0 + cc, s - 1);
+        const int64_t x = row + (int64_t)col * n;
+        tv[0][u] = fr[x];
+        tv[1][u] = fi[x];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, rr = e & 63, cc = e >> 6, row = rb + rr, col = i0 + cc;
+        T vr = tv[0][u], vi = tv[1][u];
+        if (row >= kend || col >= s || (M == 3 && row <= col)) {
+          vr = (M == 3 && row == col && row < kend && col < s) ? T(1) : T(0);
+          vi = 0;
         }
         at[0][rr][cc] = vr;
         at[1][rr][cc] = vi;
@@ -1737,33 +1744,23 @@ __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) 
 }
 
 // interface GEMV: mode 0: YG = X v_root ; mode 1: v_root = YG - X h.
-// Workgroup = 64 rows x 4 column groups; the right-hand side is staged in LDS
-// in chunks of 256 columns of X.
+// Workgroup = 64 rows x 4 column groups; 8 right-hand sides at a time are
+// staged in LDS (re, im interleaved per column) for 256 columns of X, and
+// each thread keeps four columns of X in flight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
-  __shared__ T redr[4][64][9], redi[4][64][9];
-  __shared__ T inr_s[256][9], ini_s[256][9];
+  __shared__ __align__(16) T xs[256 * 16];   // also the 4 x 64 x 16 reduction buffer
   const Item it = p.gemv[blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int g = f.s;
   const int64_t mr = p.mr;
-  const int m = threadIdx.x & 63, cg = threadIdx.x >> 6, r = it.i + m;
+  const int tid = threadIdx.x, m = tid & 63, cg = tid >> 6, r = it.i + m;
   const T *Xr = p.num + f.xoff;
   const T *Xi = Xr + (int64_t)g * g;
-  const T *inr, *ini;
-  T *outr, *outi;
-  const T *addr = nullptr, *addi = nullptr;
   T *yg = p.num + f.goff;              // YG: re [g x mr], im after
-  T *h = yg + 2 * (int64_t)g * mr;     // h
   T *v = p.num + f.voff;               // root vector (ld g)
-  if (mode == 0) {
-    inr = v; ini = v + (int64_t)g * mr;
-    outr = yg; outi = yg + (int64_t)g * mr;
-  } else {
-    inr = h; ini = h + (int64_t)g * mr;
-    addr = yg; addi = yg + (int64_t)g * mr;
-    outr = v; outi = v + (int64_t)g * mr;
-  }
+  const int64_t pl = (int64_t)g * mr;
+  const T *in = mode == 0 ? v : yg + 2 * pl;
   for (int j0 = 0; j0 < nrhs; j0 += 8) {
     const int nj = min(8, nrhs - j0);
     T ar[8], ai[8];
@@ -1771,53 +1768,110 @@ __global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
     for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
     for (int c0 = 0; c0 < g; c0 += 256) {
       __syncthreads();
-      for (int e = threadIdx.x; e < 256 * 8; e += 256) {
+      for (int e = tid; e < 256 * 8; e += 256) {
         const int c = e % 256, q = e / 256;
         T br = 0, bi = 0;
         if (c0 + c < g && q < nj) {
           const int64_t io = c0 + c + (int64_t)(j0 + q) * g;
-          br = inr[io];
-          bi = ini[io];
+          br = in[io];
+          bi = in[io + pl];
         }
-        inr_s[c][q] = br;
-        ini_s[c][q] = bi;
+        xs[c * 16 + q] = br;
+        xs[c * 16 + 8 + q] = bi;
       }
       __syncthreads();
       if (r < g) {
         const int cend = min(256, g - c0);
+#pragma unroll 4
         for (int c = cg; c < cend; c += 4) {
           const int64_t o = r + (int64_t)(c0 + c) * g;
-          const T xr = Xr[o], xi = Xi[o];
+          zacc(&xs[c * 16], Xr[o], Xi[o], ar, ai);
+        }
+      }
+    }
+    __syncthreads();
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            ar[q] += xr * inr_s[c][q] - xi * ini_s[c][q];
-            ai[q] += xr * ini_s[c][q] + xi * inr_s[c][q];
+    for (int q = 0; q < 8; ++q) {
+      xs[(cg * 64 + m) * 16 + q] = ar[q];
+      xs[(cg * 64 + m) * 16 + 8 + q] = ai[q];
+    }
+    __syncthreads();
+    if (r < g) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = cg + 4 * h;
+        if (q < nj) {
+          T sr = 0, si = 0;
+#pragma unroll
+          for (int gg = 0; gg < 4; ++gg) {
+            sr += xs[(gg * 64 + m) * 16 + q];
+            si += xs[(gg * 64 + m) * 16 + 8 + q];
+          }
+          const int64_t o = r + (int64_t)(j0 + q) * g;
+          if (mode == 0) {
+            yg[o] = sr;
+            yg[o + pl] = si;
+          } else {
+            v[o] = yg[o] - sr;
+            v[o + pl] = yg[o + pl] - si;
           }
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      redr[cg][m][q] = ar[q];
-      redi[cg][m][q] = ai[q];
+  }
+}
+
+// interface product on the matrix cores, for more than ZMMA_MIN right-hand
+// sides: the same two modes as k_gemv, one 64-row block of X times 64-column
+// blocks of the right-hand sides over the full inner dimension g
+template <typename T>
+__global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
+  __shared__ GemmSmem<T, T64> sm;
+  const Item it = p.gemv[blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int g = f.s, i0 = it.i;
+  const int64_t mr = p.mr, pl = (int64_t)g * mr;
+  const T *Xr = p.num + f.xoff;
+  const T *Xi = Xr + (int64_t)g * g;
+  T *yg = p.num + f.goff;
+  T *v = p.num + f.voff;
+  const T *in = mode == 0 ? v : yg + 2 * pl;
+  auto fa = [&](int m, int kk, T &re, T &im) {
+    const int r = i0 + m;
+    if (r < g) {
+      const int64_t e = r + (int64_t)kk * g;
+      re = Xr[e];
+      im = Xi[e];
     }
-    __syncthreads();
-    if (cg == 0 && r < g) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (q >= nj) break;
-        T sr = redr[0][m][q] + redr[1][m][q] + redr[2][m][q] + redr[3][m][q];
-        T si = redi[0][m][q] + redi[1][m][q] + redi[2][m][q] + redi[3][m][q];
-        const int64_t o = r + (int64_t)(j0 + q) * g;
-        if (mode == 0) {
-          outr[o] = sr;
-          outi[o] = si;
-        } else {
-          outr[o] = addr[o] - sr;
-          outi[o] = addi[o] - si;
-        }
+  };
+  for (int j0 = 0; j0 < nrhs; j0 += 64) {
+    auto fb = [&](int c, int kk, T &re, T &im) {
+      if (j0 + c < nrhs) {
+        const int64_t e = kk + (int64_t)(j0 + c) * g;
+        re = in[e];
+        im = in[e + pl];
       }
-    }
+    };
+    typename V4<T>::t cr[2][2], ci[2][2];
+    gemm_tile<T, T64, false, true>(sm, 0, g, fa, fb, cr, ci);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = i0 + out_row(x), j = j0 + out_col<T>(y, i);
+          if (r < g && j < nrhs) {
+            const int64_t o = r + (int64_t)j * g;
+            if (mode == 0) {
+              yg[o] = cr[x][y][i];
+              yg[o + pl] = ci[x][y][i];
+            } else {
+              v[o] = yg[o] - cr[x][y][i];
+              v[o + pl] = yg[o + pl] - ci[x][y][i];
+            }
+          }
+        }
   }
 }
 
@@ -1945,6 +1999,18 @@ __global__ void k_r_update(KP<T> p, int nrhs) {
   }
 }
 
+// FP64 operator copy in SELL-64 order (padding entries zero); one wave per slice
+__global__ __launch_bounds__(256) void k_sell_fill(const int64_t *csrp, const int64_t *sellp, int64_t n_torn,
+                                                   const cd *vals, cd *sell) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = r >> 6;
+  if (sl * 64 >= n_torn) return;
+  const int64_t zb = sellp[sl], zw = sellp[sl + 1];
+  const int64_t rb = r < n_torn ? csrp[r] : 0, len = r < n_torn ? csrp[r + 1] - rb : 0;
+  int64_t k = 0;
+  for (int64_t z = zb + (r & 63); z < zw; z += 64, ++k) sell[z] = k < len ? vals[rb + k] : cd{0, 0};
+}
+
 // r_u = f - K u - B^T lam ; r_l = -B u ; writes the FP32 correction rhs (vf, vc)
 // and per-block sums of |r|^2 (or |f|^2 when fnorm) per column.  Columns are
 // processed 8 at a time so the operator is streamed once per 8 columns.
@@ -1976,9 +2042,13 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
             ri[q] = fv.im;
           }
         if (!fnorm) {
-          for (int64_t z = p.csrp[e]; z < p.csrp[e + 1]; ++z) {
+          // SELL-64: the wave's 64 rows form one slice, entry k of all its
+          // rows is one contiguous 1 KiB run
+          const int64_t zb = p.sellp[e >> 6], zw = p.sellp[(e >> 6) + 1];
+#pragma unroll 2
+          for (int64_t z = zb + (e & 63); z < zw; z += 64) {
             const cd a = p.vals[z];
-            const int64_t c = p.csrc[z];
+            const int64_t c = p.sellc[z];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
               if (q < nj) {
@@ -2095,7 +2165,8 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
   k.hsign = (const int32_t *)(m + P.m_hsign);
   k.rowgam = (const int32_t *)(m + P.m_rowgam);
   k.csrp = (const int64_t *)(m + P.m_csrp);
-  k.csrc = (const int32_t *)(m + P.m_csrc);
+  k.sellp = (const int64_t *)(m + P.m_sellp);
+  k.sellc = (const int32_t *)(m + P.m_sellc);
   k.gemv = (const Item *)(m + P.m_gemv);
   k.num = (T *)(ws + P.b_num);
   uint8_t *sd = ws + P.b_side;
@@ -2210,7 +2281,8 @@ static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c
   hipError_t e = run_seq<T>(P, k, P.solve_dom_fwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   if (!P.gemv_items.empty())
-    hipLaunchKernelGGL(k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 0, nrhs);
+    hipLaunchKernelGGL(nrhs > ZMMA_MIN ? k_xmma<T> : k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 0,
+                       nrhs);
   if (P.n_mult > 0)
     hipLaunchKernelGGL(k_mgather<T>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, nrhs, with_c ? 1 : 0);
   e = run_seq<T>(P, k, P.solve_aux, nrhs, st, tm);
@@ -2219,7 +2291,8 @@ static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c
     hipLaunchKernelGGL(k_hgather<T>, dim3(nblk((int64_t)P.grefs.size() * nrhs)), dim3(256), 0, st, k,
                        (int64_t)P.grefs.size(), nrhs);
   if (!P.gemv_items.empty())
-    hipLaunchKernelGGL(k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 1, nrhs);
+    hipLaunchKernelGGL(nrhs > ZMMA_MIN ? k_xmma<T> : k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 1,
+                       nrhs);
   e = run_seq<T>(P, k, P.solve_dom_bwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   return hipGetLastError();
@@ -2278,6 +2351,14 @@ hipError_t interface_inverse_out(const Plan &P, uint8_t *ws, int front, void *ou
 }
 
 // refinement helpers (FP32 factor precision only)
+hipError_t operator_copy(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st) {
+  if (P.n_torn == 0) return hipSuccess;
+  const uint8_t *m = ws + P.b_meta;
+  hipLaunchKernelGGL(k_sell_fill, dim3(nblk(((P.n_torn + 63) / 64) * 64)), dim3(256), 0, st,
+                     (const int64_t *)(m + P.m_csrp), (const int64_t *)(m + P.m_sellp), P.n_torn, (const cd *)vals,
+                     (cd *)(ws + P.b_vals));
+  return hipGetLastError();
+}
 hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st) {
   KP<float> k = make_kp<float>(P, ws, ws + P.b_vals);
   hipLaunchKernelGGL(k_r_init<float>, dim3(nblk((P.n_torn + P.n_mult) * nrhs)), dim3(256), 0, st, k, nrhs);

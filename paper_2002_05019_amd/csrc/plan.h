@@ -22,8 +22,8 @@ enum LaunchKind : int32_t {
   L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
   L_INVSYRK,    // X = P^T Z^T D^-1 Z P
   L_SYRK2,      // trailing update on 128 x 128 tiles (512 threads)
-  L_FORK,       // side stream waits for the main stream (no kernel)
-  L_JOIN,       // main stream waits for the side stream (no kernel)
+  L_FORK,       // the side stream waits for the main stream (no kernel)
+  L_JOIN,       // the main stream waits for the side stream (no kernel)
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)
@@ -61,8 +61,8 @@ struct Launch {
 // the caller; null stream = everything on the main stream).
 struct SideStream {
   void *stream = nullptr;   // hipStream_t
-  void *fork = nullptr;     // hipEvent_t
-  void *join = nullptr;     // hipEvent_t
+  void *fork = nullptr;     // hipEvent_t, recorded on the main stream
+  void *join = nullptr;     // hipEvent_t, recorded on the side stream
 };
 
 // Optional per-kernel event timer (diagnostics): brackets every launch of
@@ -84,6 +84,13 @@ struct Plan {
   std::vector<int64_t> dom_nnz;      // first value index of each domain
   std::vector<int64_t> csr_ptr;      // torn system CSR (global rows/cols), n_torn + 1
   std::vector<int32_t> csr_col;
+  // SELL-64 copy of the torn operator for the FP64 refinement residual:
+  // slices of 64 consecutive rows, slice s holds width w_s = (sell_ptr[s+1] -
+  // sell_ptr[s]) / 64 entries per row, entry k of row 64 s + l at
+  // sell_ptr[s] + 64 k + l; padding entries have column 0 and value 0
+  std::vector<int64_t> sell_ptr;
+  std::vector<int32_t> sell_col;
+  int64_t nnz_sell = 0;
   std::vector<std::vector<int32_t>> gamma;   // sorted interface dofs per domain
   std::vector<int32_t> gamma_front;          // interface-root front id per domain (-1 if none)
 
@@ -126,7 +133,7 @@ struct Plan {
   int64_t b_meta = 0, b_num = 0, b_side = 0, b_vals = 0, b_r64 = 0, b_status = 0, b_total = 0;
   // offsets (bytes) of each meta array inside the meta blob
   int64_t m_fronts, m_vars, m_cfront, m_crmap, m_rmap, m_spairs, m_aux, m_gpos, m_gsign,
-      m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_csrc;
+      m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_sellp, m_sellc;
   std::vector<uint8_t> meta;           // serialised meta blob
   // FP64 refinement vectors (doubles, planar) inside the r64 region
   int64_t r_u = 0, r_l = 0, r_ru = 0, r_rl = 0, r_norm = 0, r_fnorm = 0, r_part = 0;
@@ -144,6 +151,7 @@ struct SetupOptions {
   int32_t aux_leaf = 256;
   int32_t verbose = 0;
   int32_t schur_tile[TILE_BUCKETS] = {0, 0, 0, 0, 0};   // 64 or 128; 0 = default
+  int32_t verify = 0;   // check the factorisation's stream ordering
 };
 
 struct ProblemView {
@@ -166,5 +174,8 @@ std::string validate_problem(const ProblemView &p, int *code);
 
 // Builds the full plan (symbolic analysis, schedule, workspace layout).
 std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &plan);
+// "" if every pair of launches of `seq` on different streams that the
+// fork / join points leave unordered touches disjoint data, else a message
+std::string check_schedule(const Plan &P, const std::vector<Launch> &seq);
 
 }  // namespace dd

@@ -1,0 +1,152 @@
+// Host verification of the factorisation's stream schedule.
+//
+// The factorisation sequence spreads its launches over the main stream and
+// side streams, ordered by fork (a side stream waits for the main stream)
+// and join (the main stream waits for a side stream) points.  This check
+// replays those ordering rules with vector clocks and, for every pair of
+// launches on different streams that are not ordered, compares what their
+// work items read and write: rectangles of a front's matrix, of its two W
+// buffers and of its pivot arrays.  Kernels other than the column / trailing
+// updates, the pivot tile and the panel solve are treated as touching
+// everything, so they must never overlap a side-stream launch.
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+#include "plan.h"
+
+namespace dd {
+namespace {
+
+enum Space { SP_A = 0, SP_W0 = 1, SP_W1 = 2, SP_PIV = 3, SP_ALL = 4 };
+
+struct Acc {
+  int sp;
+  int r0, r1, c0, c1;   // half-open row and column ranges
+  bool w;
+};
+
+using FrontAcc = std::map<int, std::vector<Acc>>;
+
+// Read and write sets of one launch, per front (front -1: everything).
+FrontAcc accesses(const Plan &P, const Launch &L) {
+  FrontAcc out;
+  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_PANEL && L.kind != L_TRSM) {
+    out[-1].push_back({SP_ALL, 0, 0, 0, 0, true});
+    return out;
+  }
+  for (int64_t x = 0; x < L.count; ++x) {
+    const Item &it = P.items[L.first + x];
+    const FrontDev &d = P.fronts[it.f];
+    const int n = d.n;
+    std::vector<Acc> &v = out[it.f];
+    if (L.kind == L_SYRK || L.kind == L_SYRK2) {
+      // A[r, q] -= sum_kk L[r, kk] W[q, kk - k]: a column update of the
+      // pivot tile q0 (q0 inside the outer block) or a trailing tile
+      const int ts = L.kind == L_SYRK ? 64 : 128;
+      const int k = it.k, r0 = it.i, q0 = it.j, bend = std::min(k + KBLK, d.s);
+      const bool colupd = q0 < bend;
+      const int kend = colupd ? q0 : bend, qend = colupd ? std::min(q0 + NB, d.s) : n;
+      const int r1 = std::min(r0 + ts, n), q1 = std::min(q0 + ts, qend);
+      const int wb = (k / KBLK) & 1 ? SP_W1 : SP_W0;
+      v.push_back({SP_A, r0, r1, k, kend, false});
+      v.push_back({wb, q0, q1, 0, kend - k, false});
+      v.push_back({SP_A, r0, r1, q0, q1, true});
+    } else if (L.kind == L_PANEL) {
+      const int k = it.k, b = std::min(NB, d.s - k);
+      v.push_back({SP_A, k, k + b, k, k + b, true});
+      v.push_back({SP_PIV, k, k + b, 0, 1, true});
+    } else {
+      // W = A21 P^T L11^-T and L21 for rows [r0, r0 + GT) of pivot tile k
+      const int k = it.k, r0 = it.i, j = it.j, b = std::min(NB, d.s - k);
+      const int r1 = std::min(r0 + GT, n);
+      const int wb = ((k - j) / KBLK) & 1 ? SP_W1 : SP_W0;
+      v.push_back({SP_A, k, k + b, k, k + b, false});
+      v.push_back({SP_PIV, k, k + b, 0, 1, false});
+      v.push_back({SP_A, r0, r1, k, k + b, true});
+      v.push_back({wb, r0, r1, j, j + b, true});
+    }
+  }
+  return out;
+}
+
+bool clash(const Acc &a, const Acc &b) {
+  if (a.sp == SP_ALL || b.sp == SP_ALL) return true;
+  if (a.sp != b.sp || !(a.w || b.w)) return false;
+  return a.r0 < b.r1 && b.r0 < a.r1 && a.c0 < b.c1 && b.c0 < a.c1;
+}
+
+// first conflicting pair of two launches' access sets, or false
+bool conflict(const FrontAcc &a, const FrontAcc &b, int *front) {
+  for (const auto &ka : a) {
+    for (const auto &kb : b) {
+      if (ka.first != -1 && kb.first != -1 && ka.first != kb.first) continue;
+      for (const Acc &x : ka.second)
+        for (const Acc &y : kb.second)
+          if (clash(x, y)) {
+            *front = ka.first >= 0 ? ka.first : kb.first;
+            return true;
+          }
+    }
+  }
+  return false;
+}
+
+}  // namespace
+
+std::string check_schedule(const Plan &P, const std::vector<Launch> &seq) {
+  constexpr int NS = 3;
+  using VC = std::array<int64_t, NS>;
+  VC clk[NS] = {};
+  struct Ev {
+    int st;
+    size_t pos;   // index in seq
+    VC vc;
+    FrontAcc acc;
+  };
+  std::vector<Ev> ev;
+  std::vector<size_t> by_stream[NS];   // indices into ev
+  for (size_t j = 0; j < seq.size(); ++j) {
+    const Launch &L = seq[j];
+    if (L.side < 0 || L.side >= NS) return "launch " + std::to_string(j) + ": bad stream";
+    if (L.kind == L_FORK || L.kind == L_JOIN) {
+      if (L.side == 0) return "sync point " + std::to_string(j) + " on the main stream";
+      const int x = L.side;
+      VC &to = L.kind == L_FORK ? clk[x] : clk[0];
+      const VC &from = L.kind == L_FORK ? clk[0] : clk[x];
+      for (int i = 0; i < NS; ++i) to[i] = std::max(to[i], from[i]);
+      continue;
+    }
+    const int st = L.side;
+    clk[st][st]++;
+    Ev e{st, j, clk[st], accesses(P, L)};
+    // every earlier launch of another stream that does not happen before this one
+    for (int s = 0; s < NS; ++s) {
+      if (s == st) continue;
+      for (size_t q = by_stream[s].size(); q-- > 0;) {
+        const Ev &a = ev[by_stream[s][q]];
+        if (a.vc[s] <= e.vc[s]) break;   // a (and all before it on s) happen before e
+        int front = -1;
+        if (conflict(a.acc, e.acc, &front)) {
+          char msg[256];
+          snprintf(msg, sizeof msg,
+                   "unordered launches %zu (kind %d, stream %d) and %zu (kind %d, stream %d) touch front %d",
+                   a.pos, seq[a.pos].kind, a.st, j, L.kind, st, front);
+          return msg;
+        }
+      }
+    }
+    by_stream[st].push_back(ev.size());
+    ev.push_back(std::move(e));
+  }
+  for (int s = 1; s < NS; ++s)
+    for (int i = 0; i < NS; ++i)
+      if (clk[s][i] > clk[0][i]) return "side stream " + std::to_string(s) + " not joined at the end";
+  return std::string();
+}
+
+}  // namespace dd

@@ -400,6 +400,21 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     for (int32_t r = 0; r <= p.n[i]; ++r) P.csr_ptr[P.dom_row[i] + r] = P.dom_nnz[i] + p.rowptr[i][r];
     for (int64_t e = 0; e < p.nnz[i]; ++e) P.csr_col[P.dom_nnz[i] + e] = (int32_t)(P.dom_row[i] + p.colind[i][e]);
   }
+  if (o.precision != 0) {
+    const int64_t nsl = (P.n_torn + 63) / 64;
+    P.sell_ptr.assign(nsl + 1, 0);
+    for (int64_t sl = 0; sl < nsl; ++sl) {
+      int64_t w = 0;
+      for (int64_t r = sl * 64; r < std::min(P.n_torn, sl * 64 + 64); ++r) w = std::max(w, P.csr_ptr[r + 1] - P.csr_ptr[r]);
+      P.sell_ptr[sl + 1] = P.sell_ptr[sl] + 64 * w;
+    }
+    P.nnz_sell = P.sell_ptr[nsl];
+    P.sell_col.assign(P.nnz_sell, 0);
+    for (int64_t r = 0; r < P.n_torn; ++r) {
+      const int64_t base = P.sell_ptr[r / 64] + (r % 64);
+      for (int64_t k = 0; k < P.csr_ptr[r + 1] - P.csr_ptr[r]; ++k) P.sell_col[base + 64 * k] = P.csr_col[P.csr_ptr[r] + k];
+    }
+  }
 
   // interface dofs per domain (sorted) and the multiplier entries
   P.gamma.assign(p.n_dom, {});
@@ -976,18 +991,19 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       for (int tj = 0; tj <= ti; ++tj) out.push_back({f, o, kend + ti * ts, kend + tj * ts});
   };
   // stream synchronisation points of the look-ahead (no kernel)
-  auto sync = [&](std::vector<Launch> &seq, int kind) {
+  auto sync = [&](std::vector<Launch> &seq, int kind, int side) {
     Launch L{};
     L.kind = kind;
     L.count = 0;
     L.first = 0;
     L.flops = 0;
+    L.side = side;
     seq.push_back(L);
   };
-  auto push_side = [&](std::vector<Launch> &seq, int kind, const std::vector<Item> &its) {
+  auto push_on = [&](std::vector<Launch> &seq, int kind, const std::vector<Item> &its, int side) {
     const size_t before = seq.size();
     push(seq, kind, its);
-    if (seq.size() > before) seq.back().side = 1;
+    if (seq.size() > before) seq.back().side = side;
   };
   // Outer blocks of KBLK columns.  Inside a block each pivot tile gets the
   // block's earlier tiles (column update), its pivot-tile factorisation and
@@ -1035,17 +1051,17 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
           item_pad += a * (a + 1) / 2 - c * (c + 1) / 2;
         }
       }
-      if (pending) sync(seq, L_JOIN);
+      if (pending) sync(seq, L_JOIN, 1);
       push(seq, L_SYRK, syr[0]);
       push(seq, L_SYRK2, syr2[0]);
       pending = !syr[1].empty() || !syr2[1].empty();
       if (pending) {
-        sync(seq, L_FORK);
-        push_side(seq, L_SYRK, syr[1]);
-        push_side(seq, L_SYRK2, syr2[1]);
+        sync(seq, L_FORK, 1);
+        push_on(seq, L_SYRK, syr[1], 1);
+        push_on(seq, L_SYRK2, syr2[1], 1);
       }
     }
-    if (pending) sync(seq, L_JOIN);
+    if (pending) sync(seq, L_JOIN, 1);
   };
   auto assemble = [&](std::vector<Launch> &seq, const std::vector<int> &fs, bool aux) {
     std::vector<Item> as, sc, ag;
@@ -1283,7 +1299,8 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.m_items = put(P.items.data(), P.items.size() * sizeof(Item));
   P.m_gemv = put(P.gemv_items.data(), P.gemv_items.size() * sizeof(Item));
   P.m_csrp = put(P.csr_ptr.data(), P.csr_ptr.size() * 8);
-  P.m_csrc = put(P.csr_col.data(), P.csr_col.size() * 4);
+  P.m_sellp = put(P.sell_ptr.data(), P.sell_ptr.size() * 8);
+  P.m_sellc = put(P.sell_col.data(), P.sell_col.size() * 4);
 
   // ------------------------------------------------------------ workspace (bytes)
   auto A256 = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
@@ -1292,7 +1309,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.b_num = b; b = A256(b + P.t_elems * (int64_t)P.elem);
   P.b_side = b; b = A256(b + P.side_n * (16 + 16 + 4 + 4));
   P.b_vals = b;
-  if (P.precision != 0) b = A256(b + P.nnz_total * 16);
+  if (P.precision != 0) b = A256(b + P.nnz_sell * 16);   // SELL-64 FP64 operator copy
   P.b_r64 = b;
   if (P.precision != 0) {
     int64_t r = 0;
