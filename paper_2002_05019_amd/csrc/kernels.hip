@@ -114,22 +114,37 @@ using T64 = Tile<64, 64, 2, 2>;      // 256 threads, 2 x 2 blocks per wave
 using T128 = Tile<128, 128, 2, 4>;   // 512 threads, 4 x 2 blocks per wave
 
 template <typename T, class TL>
-struct GemmSmem {
+struct alignas(16) GemmSmem {
   T a[2][TK][TL::BM + 4];
   T b[2][TK][TL::BN + 4];
 };
+
+// four consecutive elements from an address aligned to the element only
+// (one or two dwordx4 loads)
+typedef float f4u __attribute__((ext_vector_type(4))) __attribute__((aligned(4)));
+typedef double d2u __attribute__((ext_vector_type(2))) __attribute__((aligned(8)));
+__device__ __forceinline__ void load4(const float *p, float (&v)[4]) {
+  const f4u x = *reinterpret_cast<const f4u *>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void load4(const double *p, double (&v)[4]) {
+  const d2u x = reinterpret_cast<const d2u *>(p)[0], y = reinterpret_cast<const d2u *>(p)[1];
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
 
 // Accumulates a BM x BN complex tile P = sum_k A(m,k) B(c,k) over k in
 // [kbeg, kend).  fa(m, k, re, im) / fb(c, k, re, im) return operand values
 // (and must leave zeros outside their valid range).  AK / BK select the
 // thread mapping of the loads: true when the operand is contiguous along k.
 // The next K chunk is fetched into registers while the current one is
-// multiplied.
-template <typename T, class TL, bool AK, bool BK, class FA, class FB>
+// multiplied.  With VW = 4 (operands contiguous along m only) each thread
+// fetches four consecutive m of one k: fa(m0, k, re[4], im[4]).
+template <typename T, class TL, bool AK, bool BK, int VW = 1, class FA, class FB>
 __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int kend, FA fa, FB fb,
                                           typename V4<T>::t (&cr)[TL::XB][TL::YB],
                                           typename V4<T>::t (&ci)[TL::XB][TL::YB]) {
   constexpr int NTH = TL::NTH, XB = TL::XB, YB = TL::YB, RA = TL::REPA, RB = TL::REPB;
+  static_assert(VW == 1 || (VW == 4 && !AK && !BK && RA % 4 == 0 && RB % 4 == 0), "vector fetch layout");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w / TL::WC, wc = w % TL::WC;
 #pragma unroll
   for (int x = 0; x < XB; ++x)
@@ -145,36 +160,82 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
   auto mb_ = [&](int rep) { return BK ? tid / TK + (NTH / TK) * rep : tid % TL::BN; };
   auto kb_ = [&](int rep) { return BK ? tid % TK : tid / TL::BN + (NTH / TL::BN) * rep; };
   T ra[2][RA], rb[2][RB];
+  // vector layout: rep e of group g covers m = (tid % (BM/4)) * 4 + e at
+  // k = tid / (BM/4) + (4 NTH / BM) g
+  auto va_m = [&](int g) { return (tid % (TL::BM / 4)) * 4; };
+  auto va_k = [&](int g) { return tid / (TL::BM / 4) + (4 * NTH / TL::BM) * g; };
+  auto vb_m = [&](int g) { return (tid % (TL::BN / 4)) * 4; };
+  auto vb_k = [&](int g) { return tid / (TL::BN / 4) + (4 * NTH / TL::BN) * g; };
   auto fetch = [&](int k0) {
+    if constexpr (VW == 4) {
 #pragma unroll
-    for (int rep = 0; rep < RA; ++rep) {
-      const int m = ma_(rep), k = ka_(rep);
-      T re = 0, im = 0;
-      if (k0 + k < kend) fa(m, k0 + k, re, im);
-      ra[0][rep] = re;
-      ra[1][rep] = im;
-    }
+      for (int g = 0; g < RA / 4; ++g) {
+        T re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+        if (k0 + va_k(g) < kend) fa(va_m(g), k0 + va_k(g), re, im);
 #pragma unroll
-    for (int rep = 0; rep < RB; ++rep) {
-      const int m = mb_(rep), k = kb_(rep);
-      T re = 0, im = 0;
-      if (k0 + k < kend) fb(m, k0 + k, re, im);
-      rb[0][rep] = re;
-      rb[1][rep] = im;
+        for (int e = 0; e < 4; ++e) {
+          ra[0][4 * g + e] = re[e];
+          ra[1][4 * g + e] = im[e];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < RB / 4; ++g) {
+        T re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+        if (k0 + vb_k(g) < kend) fb(vb_m(g), k0 + vb_k(g), re, im);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          rb[0][4 * g + e] = re[e];
+          rb[1][4 * g + e] = im[e];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < RA; ++rep) {
+        const int m = ma_(rep), k = ka_(rep);
+        T re = 0, im = 0;
+        if (k0 + k < kend) fa(m, k0 + k, re, im);
+        ra[0][rep] = re;
+        ra[1][rep] = im;
+      }
+#pragma unroll
+      for (int rep = 0; rep < RB; ++rep) {
+        const int m = mb_(rep), k = kb_(rep);
+        T re = 0, im = 0;
+        if (k0 + k < kend) fb(m, k0 + k, re, im);
+        rb[0][rep] = re;
+        rb[1][rep] = im;
+      }
     }
   };
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
     __syncthreads();
+    if constexpr (VW == 4) {
 #pragma unroll
-    for (int rep = 0; rep < RA; ++rep) {
-      sm.a[0][ka_(rep)][ma_(rep)] = ra[0][rep];
-      sm.a[1][ka_(rep)][ma_(rep)] = ra[1][rep];
-    }
+      for (int g = 0; g < RA / 4; ++g)
 #pragma unroll
-    for (int rep = 0; rep < RB; ++rep) {
-      sm.b[0][kb_(rep)][mb_(rep)] = rb[0][rep];
-      sm.b[1][kb_(rep)][mb_(rep)] = rb[1][rep];
+        for (int e = 0; e < 4; ++e) {
+          sm.a[0][va_k(g)][va_m(g) + e] = ra[0][4 * g + e];
+          sm.a[1][va_k(g)][va_m(g) + e] = ra[1][4 * g + e];
+        }
+#pragma unroll
+      for (int g = 0; g < RB / 4; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          sm.b[0][vb_k(g)][vb_m(g) + e] = rb[0][4 * g + e];
+          sm.b[1][vb_k(g)][vb_m(g) + e] = rb[1][4 * g + e];
+        }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < RA; ++rep) {
+        sm.a[0][ka_(rep)][ma_(rep)] = ra[0][rep];
+        sm.a[1][ka_(rep)][ma_(rep)] = ra[1][rep];
+      }
+#pragma unroll
+      for (int rep = 0; rep < RB; ++rep) {
+        sm.b[0][kb_(rep)][mb_(rep)] = rb[0][rep];
+        sm.b[1][kb_(rep)][mb_(rep)] = rb[1][rep];
+      }
     }
     __syncthreads();
     if (k0 + TK < kend) fetch(k0 + TK);
@@ -795,24 +856,43 @@ __global__ __launch_bounds__(TL::NTH) void k_syrk(KP<T> p, int64_t first) {
   T *fi = fr + (int64_t)n * n;
   const T *Wr = p.num + f.woff + ((k / KBLK) & 1) * f.wstride;   // the outer block's W buffer
   const T *Wi = Wr + (int64_t)n * f.wcols;
-  auto fa = [&](int m, int kk, T &re, T &im) {
+  // four consecutive rows of a column: one vector load each plane when all
+  // four are in range
+  auto fa = [&](int m, int kk, T (&re)[4], T (&im)[4]) {
     const int r = r0 + m;
-    if (r < n) {
-      const int64_t o = r + (int64_t)kk * n;
-      re = fr[o];
-      im = fi[o];
+    const int64_t o = r + (int64_t)kk * n;
+    if (r + 3 < n) {
+      load4(fr + o, re);
+      load4(fi + o, im);
+    } else {
+      // clamped rows, selected afterwards (no per-element branches)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t oe = min(r + e, n - 1) + (int64_t)kk * n;
+        const T xr = fr[oe], xi = fi[oe];
+        re[e] = r + e < n ? xr : T(0);
+        im[e] = r + e < n ? xi : T(0);
+      }
     }
   };
-  auto fb = [&](int c, int kk, T &re, T &im) {
+  auto fb = [&](int c, int kk, T (&re)[4], T (&im)[4]) {
     const int q = q0 + c;
-    if (q < qend) {
-      const int64_t o = q + (int64_t)(kk - k) * n;
-      re = Wr[o];
-      im = Wi[o];
+    const int64_t o = q + (int64_t)(kk - k) * n;
+    if (q + 3 < qend) {
+      load4(Wr + o, re);
+      load4(Wi + o, im);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t oe = min(q + e, qend - 1) + (int64_t)(kk - k) * n;
+        const T xr = Wr[oe], xi = Wi[oe];
+        re[e] = q + e < qend ? xr : T(0);
+        im[e] = q + e < qend ? xi : T(0);
+      }
     }
   };
   typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
-  gemm_tile<T, TL, false, false>(sm, k, kend, fa, fb, cr, ci);
+  gemm_tile<T, TL, false, false, 4>(sm, k, kend, fa, fb, cr, ci);
   const bool diag = (r0 == q0);
 #pragma unroll
   for (int x = 0; x < TL::XB; ++x)
