@@ -132,6 +132,25 @@ __device__ __forceinline__ void load4(const double *p, double (&v)[4]) {
   v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
 }
 
+// elements x0 .. x0 + 3 of a column (planes pr / pi, element x at offset x):
+// one vector load per plane when x0 + 3 < lim, else clamped to lim - 1 and
+// zero from lim on (lim >= 1)
+template <typename T>
+__device__ __forceinline__ void col4(const T *pr, const T *pi, int x0, int lim, T (&re)[4], T (&im)[4]) {
+  if (x0 + 3 < lim) {
+    load4(pr + x0, re);
+    load4(pi + x0, im);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int x = min(x0 + e, lim - 1);
+      const T a = pr[x], b = pi[x];
+      re[e] = x0 + e < lim ? a : T(0);
+      im[e] = x0 + e < lim ? b : T(0);
+    }
+  }
+}
+
 // Accumulates a BM x BN complex tile P = sum_k A(m,k) B(c,k) over k in
 // [kbeg, kend).  fa(m, k, re, im) / fb(c, k, re, im) return operand values
 // (and must leave zeros outside their valid range).  AK / BK select the
@@ -778,28 +797,27 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
   const int32_t *pm = p.perm + f.soff + k;
-  auto fa = [&](int m, int kk, T &re, T &im) {
-    const int r = r0 + m;
-    if (r < n && kk < b) {
-      const int64_t o = r + (int64_t)(k + pm[kk]) * n;
-      re = fr[o];
-      im = fi[o];
+  // four consecutive rows of one column (vector loads, clamped tails)
+  auto fa = [&](int m, int kk, T (&re)[4], T (&im)[4]) {
+    if (kk < b) {
+      const int64_t col = (int64_t)(k + pm[kk]) * n;
+      col4(fr + col, fi + col, r0 + m, n, re, im);
     }
   };
-  auto fb = [&](int c, int kk, T &re, T &im) {
-    if (c < b && kk <= c) {
-      if (kk == c) {
-        re = 1;
-        im = 0;
-      } else {
-        const int64_t o = (k + c) + (int64_t)(k + kk) * n;
-        re = fr[o];
-        im = fi[o];
-      }
+  // L11^-1 (unit lower, stored strictly below the diagonal): entries
+  // (c .. c+3, kk) of the tile
+  auto fb = [&](int c, int kk, T (&re)[4], T (&im)[4]) {
+    const int64_t col = k + (int64_t)(k + kk) * n;
+    col4(fr + col, fi + col, c, b, re, im);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool below = kk < c + e;
+      re[e] = below ? re[e] : (kk == c + e && c + e < b ? T(1) : T(0));
+      im[e] = below ? im[e] : T(0);
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, false>(sm, 0, b, fa, fb, cr, ci);
+  gemm_tile<T, T64, false, false, 4>(sm, 0, b, fa, fb, cr, ci);
   // W buffer of the outer block starting at k - it.j
   T *Wr = p.num + f.woff + (((k - it.j) / KBLK) & 1) * f.wstride;
   T *Wi = Wr + (int64_t)n * f.wcols;
@@ -978,19 +996,23 @@ __global__ __launch_bounds__(256) void k_zrec2(KP<T> p, int64_t first) {
   const int m0 = it.k, r0 = it.i, c0 = it.j, n = f.n, s = f.s;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
-  auto fa = [&](int m, int kk, T &re, T &im) {   // Z(r0 + m, kk)
+  auto fa = [&](int m, int kk, T (&re)[4], T (&im)[4]) {   // Z(r0 + m .. + 3, kk)
     const int r = r0 + m;
-    if (r < s) zval(fr, fi, n, r, kk, re, im);
-  };
-  auto fb = [&](int c, int kk, T &re, T &im) {   // T1(kk, c0 + c), stored at (c0 + c, kk)
-    if (c0 + c < m0) {
-      const int64_t o = (c0 + c) + (int64_t)kk * n;
-      re = fr[o];
-      im = fi[o];
+    const int64_t col = (int64_t)kk * n;
+    col4(fr + col, fi + col, r, s, re, im);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool below = r + e > kk;
+      re[e] = below ? re[e] : (r + e == kk && r + e < s ? T(1) : T(0));
+      im[e] = below ? im[e] : T(0);
     }
   };
+  auto fb = [&](int c, int kk, T (&re)[4], T (&im)[4]) {   // T1(kk, c0 + c ..), stored at (c0 + c .., kk)
+    const int64_t col = (int64_t)kk * n;
+    col4(fr + col, fi + col, c0 + c, m0, re, im);
+  };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, false>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
+  gemm_tile<T, T64, false, false, 4>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
