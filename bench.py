@@ -127,6 +127,48 @@ def recorded_traffic(workload, tiles):
     return rec["bytes_per_launch"]
 
 
+def record_traffic(calib_f, calib_w, syrk_f, syrk_w, calib_mib, workload, tiles):
+    """Writes the per-launch HBM traffic record of the Schur update from four
+    rocprofv3 --pmc output folders (FETCH_SIZE then WRITE_SIZE of a device
+    copy of calib_mib MiB, and of a run with the given workload and tiles)."""
+    import csv
+    import hashlib
+
+    def rows(d):
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            return list(csv.DictReader(fh))
+
+    def copy_kib(d, counter):
+        v = [float(r["Counter_Value"]) for r in rows(d)
+             if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
+        if not v:
+            raise SystemExit(f"no copy kernel with {counter} in {d}")
+        return sum(v)
+
+    def syrk_kib(d, counter):
+        v = [float(r["Counter_Value"]) for r in rows(d)
+             if r["Counter_Name"] == counter
+             and r["Kernel_Name"].replace("void ", "", 1).startswith("dd::k_syrk<float")]
+        if not v:
+            raise SystemExit(f"no Schur-update launch with {counter} in {d}")
+        return sum(v) / len(v), len(v)
+
+    true_kib = calib_mib * 1024.0
+    sf, sw = true_kib / copy_kib(calib_f, "FETCH_SIZE"), true_kib / copy_kib(calib_w, "WRITE_SIZE")
+    (fk, n), (wk, _) = syrk_kib(syrk_f, "FETCH_SIZE"), syrk_kib(syrk_w, "WRITE_SIZE")
+    with open(os.path.join(ROOT, "paper_2002_05019_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()
+    rec = {"kernel": "k_syrk<float, Tile<64,64,2,2>> (Schur update, FP32+refine path)", "workload": workload,
+           "schur_tile_by_front_size": tiles, "launches": n,
+           "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
+           "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
+           "bytes_per_launch": int(round((fk * sf + wk * sw) * 1024)), "kernels_hip_sha256": h}
+    path = os.path.join(ROOT, "profiles", f"schur_update_{workload}_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    log(f"[bench] wrote {path}: {rec['bytes_per_launch'] / 1e6:.1f} MB per launch over {n} launches")
+
+
 def cpu_baseline(case, solver, budget_s=30.0):
     """The oracle's per-domain elimination (SuperLU factorisation + interface
     inverse) on interior domains, timed on the host; scaled to TFLOP/s with the
@@ -168,7 +210,15 @@ def main():
                          "extra factorisation after them (then the timed steps replay graphs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only copy a buffer of this many MiB on the device and exit (counter calibration)")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("CALIB_F", "CALIB_W", "PMC_F", "PMC_W"),
+                    help="write the Schur-update traffic record from four rocprofv3 --pmc folders (no GPU "
+                         "work): FETCH_SIZE / WRITE_SIZE of a --copy-calib-mib run, then of a run with "
+                         "--workload and --tiles")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic, calib_mib=args.copy_calib_mib or 1024, workload=args.workload,
+                       tiles=[int(t) for t in (args.tiles or "64,64,64,64,64").split(",")])
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the solver is single-GPU); got --gpus {args.gpus}",
               file=sys.stderr)
