@@ -13,7 +13,10 @@ namespace dd {
 constexpr int NB = 64;        // pivot-tile width of the blocked LDL^T
 constexpr int GT = 64;        // output tile edge of the MFMA GEMMs
 constexpr int KBLK = 256;     // outer block (columns per trailing update)
-constexpr int FUSE_N = 384;    // fronts up to this size are substituted by one workgroup
+// fronts up to this size are substituted by one workgroup; wider ones carry
+// Z = L11^-1 and use the split products (measured faster from 64 up, with 8
+// and with 64 right-hand sides)
+constexpr int FUSE_N = 64;
 constexpr int ZKC = 256;      // K chunk of the split substitution products
 constexpr int ZMMA_MIN = 8;   // above this many right-hand sides they run on MFMA
 

@@ -1105,16 +1105,51 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
   const T *sr = p.num + (aux ? p.vd : p.vf);
   const T *si = sr + ld * mr;
   const int64_t row = r < s ? f.vbase + p.vars[f.idx + r] : -1;
-  for (int j = 0; j < nrhs; ++j) {
-    T xr = 0, xi = 0;
-    if (row >= 0) {
-      xr = sr[row + (int64_t)j * ld];
-      xi = si[row + (int64_t)j * ld];
-    }
-    vr[r + (int64_t)j * n] = xr;
-    vi[r + (int64_t)j * n] = xi;
+  // children that contribute to row r (up to 8 in registers; the rest, if
+  // any, are added in a second pass)
+  const T *cp[8];
+  int cn[8];
+  int nc = 0, ch = 0;
+  for (; ch < f.nchild && nc < 8; ++ch) {
+    const int rr = p.rmap[p.crmap[f.child + ch] + r];
+    if (rr < 0) continue;
+    const FrontDev &cf = p.F[p.cfront[f.child + ch]];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c == nc) {
+        cp[c] = p.num + cf.voff + cf.s + rr;
+        cn[c] = cf.n;
+      }
+    ++nc;
   }
-  for (int ch = 0; ch < f.nchild; ++ch) {
+  // eight right-hand sides at a time: all loads, then the stores
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    T xr[8], xi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = min(j0 + q, nrhs - 1);
+      xr[q] = row >= 0 ? sr[row + (int64_t)j * ld] : T(0);
+      xi[q] = row >= 0 ? si[row + (int64_t)j * ld] : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c >= nc) break;
+      const int64_t pl = (int64_t)cn[c] * mr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = min(j0 + q, nrhs - 1);
+        xr[q] += cp[c][(int64_t)j * cn[c]];
+        xi[q] += cp[c][(int64_t)j * cn[c] + pl];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (j0 + q < nrhs) {
+        vr[r + (int64_t)(j0 + q) * n] = xr[q];
+        vi[r + (int64_t)(j0 + q) * n] = xi[q];
+      }
+  }
+  for (; ch < f.nchild; ++ch) {
     const int rr = p.rmap[p.crmap[f.child + ch] + r];
     if (rr < 0) continue;
     const FrontDev &cf = p.F[p.cfront[f.child + ch]];
@@ -1142,18 +1177,31 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
   T *vi = vr + (int64_t)n * p.mr;
   const cd d = p.dinv[sa];
   const cd d1 = pd ? p.dinv[sa + 1] : cd{0, 0}, od = pd ? p.doff[sa] : cd{0, 0};
-  for (int j = 0; j < nrhs; ++j) {
-    const int64_t o = a + (int64_t)j * n;
-    const double y0r = vr[o], y0i = vi[o];
-    if (pd == 0) {
-      vr[o] = (T)(d.re * y0r - d.im * y0i);
-      vi[o] = (T)(d.re * y0i + d.im * y0r);
-    } else {
-      const double y1r = vr[o + 1], y1i = vi[o + 1];
-      vr[o] = (T)((d.re * y0r - d.im * y0i) + (od.re * y1r - od.im * y1i));
-      vi[o] = (T)((d.re * y0i + d.im * y0r) + (od.re * y1i + od.im * y1r));
-      vr[o + 1] = (T)((od.re * y0r - od.im * y0i) + (d1.re * y1r - d1.im * y1i));
-      vi[o + 1] = (T)((od.re * y0i + od.im * y0r) + (d1.re * y1i + d1.im * y1r));
+  // eight right-hand sides at a time: all loads, then the stores (the second
+  // row of a 2 x 2 block is a valid row whenever pd == 1)
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    double y0r[8], y0i[8], y1r[8], y1i[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t o = a + (int64_t)min(j0 + q, nrhs - 1) * n;
+      y0r[q] = vr[o];
+      y0i[q] = vi[o];
+      y1r[q] = pd ? (double)vr[o + 1] : 0.0;
+      y1i[q] = pd ? (double)vi[o + 1] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (j0 + q >= nrhs) break;
+      const int64_t o = a + (int64_t)(j0 + q) * n;
+      if (pd == 0) {
+        vr[o] = (T)(d.re * y0r[q] - d.im * y0i[q]);
+        vi[o] = (T)(d.re * y0i[q] + d.im * y0r[q]);
+      } else {
+        vr[o] = (T)((d.re * y0r[q] - d.im * y0i[q]) + (od.re * y1r[q] - od.im * y1i[q]));
+        vi[o] = (T)((d.re * y0i[q] + d.im * y0r[q]) + (od.re * y1i[q] + od.im * y1r[q]));
+        vr[o + 1] = (T)((od.re * y0r[q] - od.im * y0i[q]) + (d1.re * y1r[q] - d1.im * y1i[q]));
+        vi[o + 1] = (T)((od.re * y0i[q] + od.im * y0r[q]) + (d1.re * y1i[q] + d1.im * y1r[q]));
+      }
     }
   }
 }
@@ -1174,9 +1222,20 @@ __global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs)
   const T *sr = p.num + (aux ? p.vl : p.vx);
   const T *si = sr + ld * mr;
   const int64_t row = f.vbase + p.vars[f.idx + r];
-  for (int j = 0; j < nrhs; ++j) {
-    vr[r + (int64_t)j * n] = sr[row + (int64_t)j * ld];
-    vi[r + (int64_t)j * n] = si[row + (int64_t)j * ld];
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    T xr[8], xi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = min(j0 + q, nrhs - 1);
+      xr[q] = sr[row + (int64_t)j * ld];
+      xi[q] = si[row + (int64_t)j * ld];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (j0 + q < nrhs) {
+        vr[r + (int64_t)(j0 + q) * n] = xr[q];
+        vi[r + (int64_t)(j0 + q) * n] = xi[q];
+      }
   }
 }
 
@@ -1196,9 +1255,20 @@ __global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) 
   T *dr = p.num + (aux ? p.vl : p.vx);
   T *di = dr + ld * mr;
   const int64_t row = f.vbase + p.vars[f.idx + r];
-  for (int j = 0; j < nrhs; ++j) {
-    dr[row + (int64_t)j * ld] = vr[r + (int64_t)j * n];
-    di[row + (int64_t)j * ld] = vi[r + (int64_t)j * n];
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    T xr[8], xi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = min(j0 + q, nrhs - 1);
+      xr[q] = vr[r + (int64_t)j * n];
+      xi[q] = vi[r + (int64_t)j * n];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (j0 + q < nrhs) {
+        dr[row + (int64_t)(j0 + q) * ld] = xr[q];
+        di[row + (int64_t)(j0 + q) * ld] = xi[q];
+      }
   }
 }
 
@@ -2128,6 +2198,11 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
   const int64_t nt = p.n_torn, nm = p.n_mult;
   for (int j0 = 0; j0 < nrhs; j0 += 8) {
     const int nj = min(8, nrhs - j0);
+    // column offsets of the pass; columns past nrhs repeat the last one (their
+    // loads are unconditional, their results are dropped)
+    int64_t jc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) jc[q] = min(j0 + q, nrhs - 1);
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0;
@@ -2137,12 +2212,11 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
       for (int q = 0; q < 8; ++q) rr[q] = ri[q] = 0;
       if (e < nt) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (q < nj) {
-            const cd fv = f[e + (j0 + q) * ldf];
-            rr[q] = fv.re;
-            ri[q] = fv.im;
-          }
+        for (int q = 0; q < 8; ++q) {
+          const cd fv = f[e + jc[q] * ldf];
+          rr[q] = fv.re;
+          ri[q] = fv.im;
+        }
         if (!fnorm) {
           // SELL-64: the wave's 64 rows form one slice, entry k of all its
           // rows is one contiguous 1 KiB run
@@ -2151,13 +2225,17 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
           for (int64_t z = zb + (e & 63); z < zw; z += 64) {
             const cd a = p.vals[z];
             const int64_t c = p.sellc[z];
+            double ur[8], ui[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-              if (q < nj) {
-                const double ur = U[c + (j0 + q) * nt], ui = U[c + (j0 + q) * nt + nt * mr];
-                rr[q] -= a.re * ur - a.im * ui;
-                ri[q] -= a.re * ui + a.im * ur;
-              }
+            for (int q = 0; q < 8; ++q) {
+              ur[q] = U[c + jc[q] * nt];
+              ui[q] = U[c + jc[q] * nt + nt * mr];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              rr[q] -= a.re * ur[q] - a.im * ui[q];
+              ri[q] -= a.re * ui[q] + a.im * ur[q];
+            }
           }
           const int gidx = p.rowgam[e];
           if (gidx >= 0) {
@@ -2166,11 +2244,10 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
               const int64_t m = p.hmult[G.beg + t];
               const double sg = p.hsign[G.beg + t];
 #pragma unroll
-              for (int q = 0; q < 8; ++q)
-                if (q < nj) {
-                  rr[q] -= sg * L[m + (j0 + q) * nm];
-                  ri[q] -= sg * L[m + (j0 + q) * nm + nm * mr];
-                }
+              for (int q = 0; q < 8; ++q) {
+                rr[q] -= sg * L[m + jc[q] * nm];
+                ri[q] -= sg * L[m + jc[q] * nm + nm * mr];
+              }
             }
           }
           T *vf = p.num + p.vf;
@@ -2186,16 +2263,18 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
         const MultRef R = p.mrefs[m];
         T *vc = p.num + p.vc;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const double sg = R.sg[t];
+            rr[q] -= sg * U[R.row[t] + jc[q] * nt];
+            ri[q] -= sg * U[R.row[t] + jc[q] * nt + nt * mr];
+          }
           if (q < nj) {
-            for (int t = 0; t < 2; ++t) {
-              const double sg = R.sg[t];
-              rr[q] -= sg * U[R.row[t] + (j0 + q) * nt];
-              ri[q] -= sg * U[R.row[t] + (j0 + q) * nt + nt * mr];
-            }
             vc[m + (j0 + q) * nm] = (T)rr[q];
             vc[m + (j0 + q) * nm + nm * mr] = (T)ri[q];
           }
+        }
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] += rr[q] * rr[q] + ri[q] * ri[q];
