@@ -1,0 +1,84 @@
+"""GPU parity on the method's degenerate cases and at the full bench size.
+
+* One domain: no multipliers and no auxiliary matrix, so the DD solve is a
+  single sparse LDL^T of the operator (section II with one domain).
+* Two domains: the auxiliary matrix is one dense block (one aux front).
+* The 48^3 bench workload, in the configuration ``bench.py`` times (tuned
+  tiles, hipGraph replay): interface inverses of sampled domains against the
+  oracle's sparse direct inverse (the oracle cannot do the whole case in
+  seconds), every column's residual on the host, and the mixed path against
+  the FP64 path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_05019_amd.problem import even_cuts
+from tests.conftest import cached_case
+from tests.test_gpu_parity import DEV, _colerr, _rhs, _solver
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_single_domain_is_one_sparse_solve(precision):
+    c = cached_case("cube12", cuts=even_cuts(12, 1))
+    assert c.n_dom == 1 and c.n_mult == 0
+    print(f"[parity] one domain cube12 {precision}", flush=True)
+    s = _solver(c, precision=precision)
+    u = s.solve(_rhs(c))
+    torch.cuda.synchronize()
+    ref = oracle.global_solve(c.A, c.f)
+    err = _colerr(c.owner_copy(u.cpu().numpy()), ref)
+    assert err < (1e-10 if precision == "fp64" else 1e-7), err
+    if precision == "fp32_refine":
+        assert s.info()["rel_resid"] <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_two_domains_dense_auxiliary_block(precision):
+    c = cached_case("cube12", cuts=((0, 12), (0, 12), (0, 6, 12)))
+    assert c.n_dom == 2 and c.n_mult > 0
+    print(f"[parity] two domains cube12 {precision}", flush=True)
+    s = _solver(c, precision=precision)
+    u, lam = s.solve(_rhs(c), return_lam=True)
+    torch.cuda.synchronize()
+    ref = oracle.serial_dd(c)
+    tol = 1e-10 if precision == "fp64" else 1e-7
+    assert _colerr(u.cpu().numpy(), ref["u"]) < tol
+    assert _colerr(lam.cpu().numpy(), ref["lam"]) < 10 * tol
+
+
+def test_full_size_sampled_parity():
+    c = cached_case("cube48")
+    print("[parity] cube48 full size: fp64 setup + tune + graph", flush=True)
+    f = _rhs(c)
+    s = _solver(c, max_rhs=8, use_graph=True)
+    s.tune()
+    vals = torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV)
+    s.factor(vals)
+    u64 = s.solve(f)
+    torch.cuda.synchronize()
+    info = s.info()
+    assert info["n_perturbed"] == 0 and info["numeric_flags"] == 0
+    # sampled interface inverses: a corner and an interior domain
+    for i in (0, 21):
+        print(f"[parity] cube48 interface inverse of domain {i}", flush=True)
+        g = c.gamma(i)
+        assert np.array_equal(s.interface_dofs(i), g)
+        X = s.interface_inverse(i).cpu().numpy()
+        R, _ = oracle.interface_inverse(c.domains[i].K, g)
+        assert np.abs(X - R).max() / np.abs(R).max() < 1e-10
+    u64 = u64.cpu().numpy()
+    assert oracle.global_residual(c, u64).max() < 1e-11
+    print("[parity] cube48 full size: fp32+refine", flush=True)
+    m = _solver(c, precision="fp32_refine", max_rhs=8, use_graph=True)
+    m.tune()
+    m.factor(vals)
+    um = m.solve(f)
+    torch.cuda.synchronize()
+    assert m.last_status == 0 and m.info()["rel_resid"] <= 1e-9
+    um = um.cpu().numpy()
+    assert oracle.global_residual(c, um).max() < 1e-8
+    assert _colerr(um, u64) < 1e-7
