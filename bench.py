@@ -148,7 +148,7 @@ def record_traffic(calib_f, calib_w, syrk_f, syrk_w, calib_mib, workload, tiles)
     def syrk_kib(d, counter):
         v = [float(r["Counter_Value"]) for r in rows(d)
              if r["Counter_Name"] == counter
-             and r["Kernel_Name"].replace("void ", "", 1).startswith("dd::k_syrk<float")]
+             and r["Kernel_Name"].replace("void ", "", 1).startswith("dd::k_syrk<float, dd::Tile<64, 64, 2, 2, 16>")]
         if not v:
             raise SystemExit(f"no Schur-update launch with {counter} in {d}")
         return sum(v) / len(v), len(v)

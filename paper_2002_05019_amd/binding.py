@@ -53,7 +53,7 @@ EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_works
            "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_tune",
            "dd_destroy", "dd_last_error"]
 TILE_BUCKETS = 5   # front sizes [0,512) [512,1024) [1024,2048) [2048,4096) [4096,...)
-KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3}
+KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3, "column_update": 4}
 
 _lib = None
 

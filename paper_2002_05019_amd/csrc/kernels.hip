@@ -83,15 +83,15 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int TK = 16;   // K chunk per LDS stage
 
 // Output tile of the MFMA GEMMs: BM x BN, WR x WC waves, each wave owning an
 // (XB*16) x (YB*16) block of 16 x 16 MFMA results.
-template <int BM_, int BN_, int WR_, int WC_>
+// TK_ is the K depth of one LDS stage.
+template <int BM_, int BN_, int WR_, int WC_, int TK_ = 16>
 struct Tile {
-  static constexpr int BM = BM_, BN = BN_, WR = WR_, WC = WC_, NTH = 64 * WR_ * WC_;
+  static constexpr int BM = BM_, BN = BN_, WR = WR_, WC = WC_, NTH = 64 * WR_ * WC_, TK = TK_;
   static constexpr int XB = BM_ / (16 * WR_), YB = BN_ / (16 * WC_);
-  static constexpr int REPA = BM_ * TK / NTH, REPB = BN_ * TK / NTH;
+  static constexpr int REPA = BM_ * TK_ / NTH, REPB = BN_ * TK_ / NTH;
   // Position of element i of result block (x, y): row (the m index) and
   // column (the c index) inside the tile.  The MFMA computes the transposed
   // block (first operand from B, second from A) so that the 16 lanes of a
@@ -111,12 +111,15 @@ struct Tile {
   }
 };
 using T64 = Tile<64, 64, 2, 2>;      // 256 threads, 2 x 2 blocks per wave
+// the same tile with 32-deep stages: half the dependent load / barrier steps
+// for the short-K GEMMs on the pivot chain (column update, panel solve)
+using T64K32 = Tile<64, 64, 2, 2, 32>;
 using T128 = Tile<128, 128, 2, 4>;   // 512 threads, 4 x 2 blocks per wave
 
 template <typename T, class TL>
 struct alignas(16) GemmSmem {
-  T a[2][TK][TL::BM + 4];
-  T b[2][TK][TL::BN + 4];
+  T a[2][TL::TK][TL::BM + 4];
+  T b[2][TL::TK][TL::BN + 4];
 };
 
 // four consecutive elements from an address aligned to the element only
@@ -162,7 +165,7 @@ template <typename T, class TL, bool AK, bool BK, int VW = 1, class FA, class FB
 __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int kend, FA fa, FB fb,
                                           typename V4<T>::t (&cr)[TL::XB][TL::YB],
                                           typename V4<T>::t (&ci)[TL::XB][TL::YB]) {
-  constexpr int NTH = TL::NTH, XB = TL::XB, YB = TL::YB, RA = TL::REPA, RB = TL::REPB;
+  constexpr int NTH = TL::NTH, XB = TL::XB, YB = TL::YB, RA = TL::REPA, RB = TL::REPB, TK = TL::TK;
   static_assert(VW == 1 || (VW == 4 && !AK && !BK && RA % 4 == 0 && RB % 4 == 0), "vector fetch layout");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w / TL::WC, wc = w % TL::WC;
 #pragma unroll
@@ -789,7 +792,7 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T, T64> sm;
+  __shared__ GemmSmem<T, T64K32> sm;
   __shared__ T wr[GT][GT + 1], wi[GT][GT + 1];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -817,7 +820,7 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, false, 4>(sm, 0, b, fa, fb, cr, ci);
+  gemm_tile<T, T64K32, false, false, 4>(sm, 0, b, fa, fb, cr, ci);
   // W buffer of the outer block starting at k - it.j
   T *Wr = p.num + f.woff + (((k - it.j) / KBLK) & 1) * f.wstride;
   T *Wi = Wr + (int64_t)n * f.wcols;
@@ -2404,6 +2407,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_TRSM: hipLaunchKernelGGL(k_trsm<T>, g, b, 0, st, k, L.first); break;
       case L_SYRK: hipLaunchKernelGGL((k_syrk<T, T64>), g, b, 0, st, k, L.first); break;
       case L_SYRK2: hipLaunchKernelGGL((k_syrk<T, T128>), g, dim3(T128::NTH), 0, st, k, L.first); break;
+      case L_UPD: hipLaunchKernelGGL((k_syrk<T, T64K32>), g, b, 0, st, k, L.first); break;
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
       case L_INVSYRK: hipLaunchKernelGGL(k_invsyrk<T>, g, b, 0, st, k, L.first); break;

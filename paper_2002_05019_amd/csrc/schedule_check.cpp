@@ -35,7 +35,7 @@ using FrontAcc = std::map<int, std::vector<Acc>>;
 // Read and write sets of one launch, per front (front -1: everything).
 FrontAcc accesses(const Plan &P, const Launch &L) {
   FrontAcc out;
-  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_PANEL && L.kind != L_TRSM) {
+  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_UPD && L.kind != L_PANEL && L.kind != L_TRSM) {
     out[-1].push_back({SP_ALL, 0, 0, 0, 0, true});
     return out;
   }
@@ -44,10 +44,10 @@ FrontAcc accesses(const Plan &P, const Launch &L) {
     const FrontDev &d = P.fronts[it.f];
     const int n = d.n;
     std::vector<Acc> &v = out[it.f];
-    if (L.kind == L_SYRK || L.kind == L_SYRK2) {
+    if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPD) {
       // A[r, q] -= sum_kk L[r, kk] W[q, kk - k]: a column update of the
       // pivot tile q0 (q0 inside the outer block) or a trailing tile
-      const int ts = L.kind == L_SYRK ? 64 : 128;
+      const int ts = L.kind == L_SYRK2 ? 128 : 64;
       const int k = it.k, r0 = it.i, q0 = it.j, bend = std::min(k + KBLK, d.s);
       const bool colupd = q0 < bend;
       const int kend = colupd ? q0 : bend, qend = colupd ? std::min(q0 + NB, d.s) : n;

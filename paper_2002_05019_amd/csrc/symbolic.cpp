@@ -907,7 +907,8 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     const FrontDev &d = P.fronts[it.f];
     const int n = d.n;
     switch (kind) {
-      case L_SYRK: {   // C(r0.., q0..) -= L21 W^T over the lower triangle
+      case L_SYRK:
+      case L_UPD: {   // C(r0.., q0..) -= L21 W^T over the lower triangle
         // item: k = first column of the outer block; j = q0.  K length:
         // trailing update (i >= block end): block width; column update: q0 - k
         const int kend = std::min(it.k + KBLK, d.s);
@@ -959,9 +960,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     L.p0 = p0;
     L.p1 = p1;
     L.flops = 0;
-    if (kind <= L_SYRK2)
+    if (kind <= L_UPD)
       for (const Item &it : its) L.flops += item_flops(kind, it);
-    const bool gemm = kind == L_SYRK || kind == L_SYRK2 || kind == L_TRSM || kind == L_ZREC1 || kind == L_ZREC2 || kind == L_INVSYRK;
+    const bool gemm = kind == L_SYRK || kind == L_SYRK2 || kind == L_UPD || kind == L_TRSM || kind == L_ZREC1 ||
+                      kind == L_ZREC2 || kind == L_INVSYRK;
     if (gemm && its.size() >= 16) {
       // Workgroup b runs on XCD b % 8: give each XCD a contiguous run of the
       // item list (items sharing an operand panel are adjacent), so that
@@ -1030,7 +1032,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
           pan.push_back({f, k, 0, 0});
           for (int r0 = k + b; r0 < d.n; r0 += GT) trs.push_back({f, k, r0, k - o});
         }
-        push(seq, L_SYRK, upd);
+        push(seq, L_UPD, upd);
         push(seq, L_PANEL, pan);
         push(seq, L_TRSM, trs);
       }
