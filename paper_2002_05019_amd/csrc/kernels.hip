@@ -1604,72 +1604,64 @@ __global__ __launch_bounds__(256) void k_bfront(KP<T> p, int64_t first, int nrhs
 //   M = 1: u(r) = sum_{c < s}  L(r, c) y(c)          s <= r < n   -> v_R -= u
 //   M = 2: u(c) = sum_{s <= r < n} L(r, c) x(r)      c < s        -> W = z - u
 //   M = 3: x(a) = sum_{c >= a} Z(c, a) t(c)          a < s        -> v(P a)
-// The right-hand sides are processed 8 at a time; an input row is staged in
-// LDS as 16 contiguous values (8 real parts, then 8 imaginary parts) and read
-// back with 16-byte broadcasts.
+// Up to 8 right-hand sides: an input row is staged in LDS as 16 contiguous
+// values (8 real parts, then 8 imaginary parts), the 16 real columns of the
+// matrix-core products below; more: the 64-column complex MFMA tile.
+//
+// The 8-RHS split products on the matrix cores: per output tile two real
+// products, P = Re(A) [Re x | Im x] and Q = Im(A) [Re x | Im x] (16 real
+// columns, none padded), then Re y = P(:, 0:8) - Q(:, 8:16) and
+// Im y = P(:, 8:16) + Q(:, 0:8).  Each of the four waves owns 16 outputs.
+// Column of result element i of a 16 x 16 block (first MFMA operand from the
+// right-hand sides): FP32 4 (lane / 16) + i, FP64 lane / 16 + 4 i; its row
+// is lane % 16.
 template <typename T>
-__device__ __forceinline__ void zacc(const T *x, T ar_, T ai_, T (&ar)[8], T (&ai)[8]) {
-  T xv[16];
-  if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float4 w = reinterpret_cast<const float4 *>(x)[u];
-      xv[4 * u] = w.x; xv[4 * u + 1] = w.y; xv[4 * u + 2] = w.z; xv[4 * u + 3] = w.w;
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double2 w = reinterpret_cast<const double2 *>(x)[u];
-      xv[2 * u] = w.x; xv[2 * u + 1] = w.y;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    ar[q] += ar_ * xv[q] - ai_ * xv[8 + q];
-    ai[q] += ar_ * xv[8 + q] + ai_ * xv[q];
-  }
+__device__ __forceinline__ int mfma_col(int lane, int i) {
+  return sizeof(T) == 8 ? (lane >> 4) + 4 * i : (lane >> 4) * 4 + i;
 }
-
-// Sums the four thread groups' accumulators (through red, 4 x 64 x 16) and
-// writes RHS columns [j0, j0 + 8) of the 64-output partial slot.
-template <typename T>
-__device__ __forceinline__ void zpart_out(T *red, const T (&ar)[8], const T (&ai)[8], T *slot, int64_t mr, int j0,
-                                          int nrhs) {
-  const int tid = threadIdx.x, o = tid & 63, g = tid >> 6;
+// combines P, Q through ps (4 x 2 x 16 x 17, may alias the caller's staging
+// buffers: a barrier comes first) and hands output o (0..63) of right-hand
+// side q < nrhs to out(o, q, re, im)
+template <typename T, class OUT>
+__device__ __forceinline__ void zq_combine(T *ps, const typename V4<T>::t &P, const typename V4<T>::t &Q, int nrhs,
+                                           OUT out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, m = lane & 15;
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    red[(g * 64 + o) * 16 + q] = ar[q];
-    red[(g * 64 + o) * 16 + 8 + q] = ai[q];
+  for (int i = 0; i < 4; ++i) {
+    const int c = mfma_col<T>(lane, i);
+    ps[((w * 2 + 0) * 16 + m) * 17 + c] = P[i];
+    ps[((w * 2 + 1) * 16 + m) * 17 + c] = Q[i];
   }
   __syncthreads();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int q = g + 4 * h;
-    if (j0 + q < nrhs) {
-      T sr = 0, si = 0;
-#pragma unroll
-      for (int gg = 0; gg < 4; ++gg) {
-        sr += red[(gg * 64 + o) * 16 + q];
-        si += red[(gg * 64 + o) * 16 + 8 + q];
-      }
-      slot[(int64_t)(j0 + q) * 64 + o] = sr;
-      slot[64 * mr + (int64_t)(j0 + q) * 64 + o] = si;
+    const int q = (lane >> 4) + 4 * h;
+    if (q < nrhs) {
+      const T *pp = ps + (w * 2 * 16 + m) * 17, *qq = ps + ((w * 2 + 1) * 16 + m) * 17;
+      out(16 * w + m, q, pp[q] - qq[8 + q], pp[8 + q] + qq[q]);
     }
   }
 }
+// into the 64-output partial slot
+template <typename T>
+__device__ __forceinline__ void zq_out(T *ps, const typename V4<T>::t &P, const typename V4<T>::t &Q, T *slot,
+                                       int64_t mr, int nrhs) {
+  zq_combine<T>(ps, P, Q, nrhs, [&](int o, int q, T re, T im) {
+    slot[(int64_t)q * 64 + o] = re;
+    slot[64 * mr + (int64_t)q * 64 + o] = im;
+  });
+}
 
-// M = 0, 1: lanes own output rows (coalesced matrix loads), the four thread
-// groups stride over the K chunk.
+// M = 0, 1 (A(o, k) a row block of the front, contiguous along o)
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_zprod_n(KP<T> p, int64_t first, int nrhs) {
+__global__ __launch_bounds__(256) void k_zq_n(KP<T> p, int64_t first, int nrhs) {
   __shared__ __align__(16) T xs[ZKC * 16];
-  __shared__ __align__(16) T red[4 * 64 * 16];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, i0 = it.i, c0 = it.j, tid = threadIdx.x;
-  const int o = tid & 63, g = tid >> 6, r = i0 + o;
+  const int n = f.n, s = f.s, i0 = it.i, c0 = it.j, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int cend = min(c0 + ZKC, M == 0 ? min(s, i0 + 64) : s);
+  const int rlim = M == 0 ? s : n;
   const int64_t mr = p.mr;
   const T *fr = p.num + f.off;
   const T *fi = fr + (int64_t)n * n;
@@ -1677,54 +1669,60 @@ __global__ __launch_bounds__(256) void k_zprod_n(KP<T> p, int64_t first, int nrh
   const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
   const int32_t *pm = p.perm + f.soff;
   T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
-  const bool live = M == 0 ? r < s : r < n;
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
-    __syncthreads();
-    for (int e = tid; e < ZKC * 8; e += 256) {
-      const int c = e % ZKC, q = e / ZKC, cc = c0 + c;
-      T br = 0, bi = 0;
-      if (cc < cend && j0 + q < nrhs) {
-        const int src = M == 0 ? (cc / NB) * NB + pm[cc] : cc;
-        const int64_t io = src + (int64_t)(j0 + q) * n;
-        br = inr[io];
-        bi = ini[io];
-      }
-      xs[c * 16 + q] = br;
-      xs[c * 16 + 8 + q] = bi;
+  for (int e = tid; e < ZKC * 8; e += 256) {
+    const int c = e % ZKC, q = e / ZKC, cc = c0 + c;
+    T br = 0, bi = 0;
+    if (cc < cend && q < nrhs) {
+      const int src = M == 0 ? (cc / NB) * NB + pm[cc] : cc;
+      const int64_t io = src + (int64_t)q * n;
+      br = inr[io];
+      bi = ini[io];
     }
-    __syncthreads();
-    T ar[8], ai[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
-    if (live) {
-#pragma unroll 4
-      for (int c = c0 + g; c < cend; c += 4) {
-        // unconditional loads (the address is inside the square front), so
-        // that the unrolled iterations keep several loads in flight
-        const int64_t e = r + (int64_t)c * n;
-        T zr = fr[e], zi = fi[e];
-        if (M == 0 && c >= r) {
-          zr = c == r ? T(1) : T(0);
-          zi = 0;
-        }
-        zacc(&xs[(c - c0) * 16], zr, zi, ar, ai);
-      }
-    }
-    zpart_out(red, ar, ai, slot, mr, j0, nrhs);
+    xs[c * 16 + q] = br;
+    xs[c * 16 + 8 + q] = bi;
   }
+  __syncthreads();
+  const int m = lane & 15, kq = lane >> 4, r = i0 + 16 * w + m;
+  const bool live = r < rlim;
+  const int rc = min(r, rlim - 1);
+  typename V4<T>::t P = {0, 0, 0, 0}, Q = {0, 0, 0, 0};
+  // 32 columns per iteration: all loads first (clamped columns, masked
+  // afterwards; the staged right-hand sides are zero past cend)
+  for (int kb = c0; kb < cend; kb += 32) {
+    T ar[8], ai[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = kb + 4 * u + kq;
+      const int64_t e = rc + (int64_t)min(c, cend - 1) * n;
+      ar[u] = fr[e];
+      ai[u] = fi[e];
+      bv[u] = xs[(kb - c0 + 4 * u + kq) * 16 + m];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = kb + 4 * u + kq;
+      T xr = ar[u], xi = ai[u];
+      if (M == 0 && c >= r) {
+        xr = c == r ? T(1) : T(0);
+        xi = 0;
+      }
+      const bool in = live && c < cend;
+      P = mfma16(bv[u], in ? xr : T(0), P);
+      Q = mfma16(bv[u], in ? xi : T(0), Q);
+    }
+  }
+  zq_out<T>(xs, P, Q, slot, mr, nrhs);
 }
 
-// M = 2, 3: lanes own output columns; 64 x 64 matrix tiles are staged in LDS
-// with coalesced loads, the four thread groups split the tile's rows.
+// M = 2, 3 (A(o, k) a column block read along its rows k): 64 x 64 tiles of
+// the front staged in LDS with coalesced loads
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_zprod_t(KP<T> p, int64_t first, int nrhs) {
+__global__ __launch_bounds__(256) void k_zq_t(KP<T> p, int64_t first, int nrhs) {
   __shared__ T at[2][64][65];
   __shared__ __align__(16) T xs[64 * 16];
-  T *red = &at[0][0][0];   // 4 x 64 x 16 <= 2 x 64 x 65
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, i0 = it.i, k0 = it.j, tid = threadIdx.x;
-  const int o = tid & 63, g = tid >> 6;
+  const int n = f.n, s = f.s, i0 = it.i, k0 = it.j, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int kend = min(k0 + ZKC, M == 2 ? n : s);
   const int64_t mr = p.mr;
   const T *fr = p.num + f.off;
@@ -1732,50 +1730,51 @@ __global__ __launch_bounds__(256) void k_zprod_t(KP<T> p, int64_t first, int nrh
   const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
   T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
-    T ar[8], ai[8];
+  const int m = lane & 15, kq = lane >> 4;
+  typename V4<T>::t P = {0, 0, 0, 0}, Q = {0, 0, 0, 0};
+  for (int rb = k0; rb < kend; rb += 64) {
+    __syncthreads();
+    T tv[2][16];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
-    for (int rb = k0; rb < kend; rb += 64) {
-      __syncthreads();
-      // clamped, unconditional loads: all 32 of a thread can be in flight
-      T tv[2][16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = tid + 256 * u, rr = e & 63, cc = e >> 6;
-        const int row = min(rb + rr, kend - 1), col = min(i0 + cc, s - 1);
-        const int64_t x = row + (int64_t)col * n;
-        tv[0][u] = fr[x];
-        tv[1][u] = fi[x];
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = tid + 256 * u, rr = e & 63, cc = e >> 6, row = rb + rr, col = i0 + cc;
-        T vr = tv[0][u], vi = tv[1][u];
-        if (row >= kend || col >= s || (M == 3 && row <= col)) {
-          vr = (M == 3 && row == col && row < kend && col < s) ? T(1) : T(0);
-          vi = 0;
-        }
-        at[0][rr][cc] = vr;
-        at[1][rr][cc] = vi;
-      }
-      for (int e = tid; e < 64 * 8; e += 256) {
-        const int rr = e & 63, q = e >> 6, row = rb + rr;
-        T br = 0, bi = 0;
-        if (row < kend && j0 + q < nrhs) {
-          const int64_t x = row + (int64_t)(j0 + q) * n;
-          br = inr[x];
-          bi = ini[x];
-        }
-        xs[rr * 16 + q] = br;
-        xs[rr * 16 + 8 + q] = bi;
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int rr = g * 16; rr < g * 16 + 16; ++rr) zacc(&xs[rr * 16], at[0][rr][o], at[1][rr][o], ar, ai);
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, rr = e & 63, cc = e >> 6;
+      const int row = min(rb + rr, kend - 1), col = min(i0 + cc, s - 1);
+      const int64_t x = row + (int64_t)col * n;
+      tv[0][u] = fr[x];
+      tv[1][u] = fi[x];
     }
-    zpart_out(red, ar, ai, slot, mr, j0, nrhs);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, rr = e & 63, cc = e >> 6, row = rb + rr, col = i0 + cc;
+      T vr = tv[0][u], vi = tv[1][u];
+      if (row >= kend || col >= s || (M == 3 && row <= col)) {
+        vr = (M == 3 && row == col && row < kend && col < s) ? T(1) : T(0);
+        vi = 0;
+      }
+      at[0][rr][cc] = vr;
+      at[1][rr][cc] = vi;
+    }
+    for (int e = tid; e < 64 * 8; e += 256) {
+      const int rr = e & 63, q = e >> 6, row = rb + rr;
+      T br = 0, bi = 0;
+      if (row < kend && q < nrhs) {
+        const int64_t x = row + (int64_t)q * n;
+        br = inr[x];
+        bi = ini[x];
+      }
+      xs[rr * 16 + q] = br;
+      xs[rr * 16 + 8 + q] = bi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 64; kk += 4) {
+      const T ar = at[0][kk + kq][16 * w + m], ai = at[1][kk + kq][16 * w + m];
+      const T b = xs[(kk + kq) * 16 + m];
+      P = mfma16(b, ar, P);
+      Q = mfma16(b, ai, Q);
+    }
   }
+  zq_out<T>(&at[0][0][0], P, Q, slot, mr, nrhs);
 }
 
 // The same split products on the MFMA GEMM tile, for many right-hand sides
@@ -1918,86 +1917,8 @@ __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) 
   }
 }
 
-// interface GEMV: mode 0: YG = X v_root ; mode 1: v_root = YG - X h.
-// Workgroup = 64 rows x 4 column groups; 8 right-hand sides at a time are
-// staged in LDS (re, im interleaved per column) for 256 columns of X, and
-// each thread keeps four columns of X in flight.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemv(KP<T> p, int mode, int nrhs) {
-  __shared__ __align__(16) T xs[256 * 16];   // also the 4 x 64 x 16 reduction buffer
-  const Item it = p.gemv[blockIdx.x];
-  const FrontDev f = p.F[it.f];
-  const int g = f.s;
-  const int64_t mr = p.mr;
-  const int tid = threadIdx.x, m = tid & 63, cg = tid >> 6, r = it.i + m;
-  const T *Xr = p.num + f.xoff;
-  const T *Xi = Xr + (int64_t)g * g;
-  T *yg = p.num + f.goff;              // YG: re [g x mr], im after
-  T *v = p.num + f.voff;               // root vector (ld g)
-  const int64_t pl = (int64_t)g * mr;
-  const T *in = mode == 0 ? v : yg + 2 * pl;
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
-    const int nj = min(8, nrhs - j0);
-    T ar[8], ai[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0;
-    for (int c0 = 0; c0 < g; c0 += 256) {
-      __syncthreads();
-      for (int e = tid; e < 256 * 8; e += 256) {
-        const int c = e % 256, q = e / 256;
-        T br = 0, bi = 0;
-        if (c0 + c < g && q < nj) {
-          const int64_t io = c0 + c + (int64_t)(j0 + q) * g;
-          br = in[io];
-          bi = in[io + pl];
-        }
-        xs[c * 16 + q] = br;
-        xs[c * 16 + 8 + q] = bi;
-      }
-      __syncthreads();
-      if (r < g) {
-        const int cend = min(256, g - c0);
-#pragma unroll 4
-        for (int c = cg; c < cend; c += 4) {
-          const int64_t o = r + (int64_t)(c0 + c) * g;
-          zacc(&xs[c * 16], Xr[o], Xi[o], ar, ai);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      xs[(cg * 64 + m) * 16 + q] = ar[q];
-      xs[(cg * 64 + m) * 16 + 8 + q] = ai[q];
-    }
-    __syncthreads();
-    if (r < g) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int q = cg + 4 * h;
-        if (q < nj) {
-          T sr = 0, si = 0;
-#pragma unroll
-          for (int gg = 0; gg < 4; ++gg) {
-            sr += xs[(gg * 64 + m) * 16 + q];
-            si += xs[(gg * 64 + m) * 16 + 8 + q];
-          }
-          const int64_t o = r + (int64_t)(j0 + q) * g;
-          if (mode == 0) {
-            yg[o] = sr;
-            yg[o + pl] = si;
-          } else {
-            v[o] = yg[o] - sr;
-            v[o + pl] = yg[o + pl] - si;
-          }
-        }
-      }
-    }
-  }
-}
-
 // interface product on the matrix cores, for more than ZMMA_MIN right-hand
-// sides: the same two modes as k_gemv, one 64-row block of X times 64-column
+// sides: mode 0: YG = X v_root; mode 1: v_root = YG - X h; one 64-row block of X times 64-column
 // blocks of the right-hand sides over the full inner dimension g
 template <typename T>
 __global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
@@ -2048,6 +1969,73 @@ __global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
           }
         }
   }
+}
+
+// interface product on the matrix cores for up to 8 right-hand sides (the
+// same two modes as k_xmma): P = Re(X) [Re in | Im in], Q = Im(X) [Re in |
+// Im in] over the full inner dimension g, the right-hand sides staged in LDS
+// 256 columns of X at a time
+template <typename T>
+__global__ __launch_bounds__(256) void k_xq(KP<T> p, int mode, int nrhs) {
+  __shared__ __align__(16) T xs[256 * 16];
+  const Item it = p.gemv[blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int g = f.s, i0 = it.i, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t mr = p.mr, pl = (int64_t)g * mr;
+  const T *Xr = p.num + f.xoff;
+  const T *Xi = Xr + (int64_t)g * g;
+  T *yg = p.num + f.goff;
+  T *v = p.num + f.voff;
+  const T *in = mode == 0 ? v : yg + 2 * pl;
+  const int m = lane & 15, kq = lane >> 4, r = i0 + 16 * w + m;
+  const bool live = r < g;
+  const int rc = min(r, g - 1);
+  typename V4<T>::t P = {0, 0, 0, 0}, Q = {0, 0, 0, 0};
+  for (int c0 = 0; c0 < g; c0 += 256) {
+    const int cend = min(c0 + 256, g);
+    __syncthreads();
+    for (int e = tid; e < 256 * 8; e += 256) {
+      const int c = e % 256, q = e / 256, cc = c0 + c;
+      T br = 0, bi = 0;
+      if (cc < cend && q < nrhs) {
+        const int64_t io = cc + (int64_t)q * g;
+        br = in[io];
+        bi = in[io + pl];
+      }
+      xs[c * 16 + q] = br;
+      xs[c * 16 + 8 + q] = bi;
+    }
+    __syncthreads();
+    for (int kb = c0; kb < cend; kb += 32) {
+      T ar[8], ai[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = kb + 4 * u + kq;
+        const int64_t e = rc + (int64_t)min(c, cend - 1) * g;
+        ar[u] = Xr[e];
+        ai[u] = Xi[e];
+        bv[u] = xs[(kb - c0 + 4 * u + kq) * 16 + m];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = live && kb + 4 * u + kq < cend;
+        P = mfma16(bv[u], ok ? ar[u] : T(0), P);
+        Q = mfma16(bv[u], ok ? ai[u] : T(0), Q);
+      }
+    }
+  }
+  zq_combine<T>(xs, P, Q, nrhs, [&](int o, int q, T re, T im) {
+    const int row = i0 + o;
+    if (row >= g) return;
+    const int64_t x = row + (int64_t)q * g;
+    if (mode == 0) {
+      yg[x] = re;
+      yg[x + pl] = im;
+    } else {
+      v[x] = yg[x] - re;
+      v[x + pl] = yg[x + pl] - im;
+    }
+  });
 }
 
 // d(p) = sum_t s_t YG_t - c(p)
@@ -2419,22 +2407,22 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case S_BFRONT: hipLaunchKernelGGL(k_bfront<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_ZP0:
         if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_n<T, 0>), g, b, 0, st, k, L.first, nrhs);
-        else hipLaunchKernelGGL((k_zprod_n<T, 0>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zq_n<T, 0>), g, b, 0, st, k, L.first, nrhs);
         break;
       case S_ZR0: hipLaunchKernelGGL((k_zred<T, 0>), g, b, 0, st, k, L.first, nrhs); break;
       case S_ZP1:
         if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_n<T, 1>), g, b, 0, st, k, L.first, nrhs);
-        else hipLaunchKernelGGL((k_zprod_n<T, 1>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zq_n<T, 1>), g, b, 0, st, k, L.first, nrhs);
         break;
       case S_ZR1: hipLaunchKernelGGL((k_zred<T, 1>), g, b, 0, st, k, L.first, nrhs); break;
       case S_ZP2:
         if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_t<T, 2>), g, b, 0, st, k, L.first, nrhs);
-        else hipLaunchKernelGGL((k_zprod_t<T, 2>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zq_t<T, 2>), g, b, 0, st, k, L.first, nrhs);
         break;
       case S_ZR2: hipLaunchKernelGGL((k_zred<T, 2>), g, b, 0, st, k, L.first, nrhs); break;
       case S_ZP3:
         if (nrhs > ZMMA_MIN) hipLaunchKernelGGL((k_zmma_t<T, 3>), g, b, 0, st, k, L.first, nrhs);
-        else hipLaunchKernelGGL((k_zprod_t<T, 3>), g, b, 0, st, k, L.first, nrhs);
+        else hipLaunchKernelGGL((k_zq_t<T, 3>), g, b, 0, st, k, L.first, nrhs);
         break;
       case S_ZR3: hipLaunchKernelGGL((k_zred<T, 3>), g, b, 0, st, k, L.first, nrhs); break;
       default: return hipErrorInvalidValue;
@@ -2466,7 +2454,7 @@ static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c
   hipError_t e = run_seq<T>(P, k, P.solve_dom_fwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   if (!P.gemv_items.empty())
-    hipLaunchKernelGGL(nrhs > ZMMA_MIN ? k_xmma<T> : k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 0,
+    hipLaunchKernelGGL(nrhs > ZMMA_MIN ? k_xmma<T> : k_xq<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 0,
                        nrhs);
   if (P.n_mult > 0)
     hipLaunchKernelGGL(k_mgather<T>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, nrhs, with_c ? 1 : 0);
@@ -2476,7 +2464,7 @@ static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c
     hipLaunchKernelGGL(k_hgather<T>, dim3(nblk((int64_t)P.grefs.size() * nrhs)), dim3(256), 0, st, k,
                        (int64_t)P.grefs.size(), nrhs);
   if (!P.gemv_items.empty())
-    hipLaunchKernelGGL(nrhs > ZMMA_MIN ? k_xmma<T> : k_gemv<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 1,
+    hipLaunchKernelGGL(nrhs > ZMMA_MIN ? k_xmma<T> : k_xq<T>, dim3(P.gemv_items.size()), dim3(256), 0, st, k, 1,
                        nrhs);
   e = run_seq<T>(P, k, P.solve_dom_bwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
