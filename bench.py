@@ -158,7 +158,7 @@ def record_traffic(calib_f, calib_w, syrk_f, syrk_w, calib_mib, workload, tiles)
     (fk, n), (wk, _) = syrk_kib(syrk_f, "FETCH_SIZE"), syrk_kib(syrk_w, "WRITE_SIZE")
     with open(os.path.join(ROOT, "paper_2002_05019_amd", "csrc", "kernels.hip"), "rb") as fh:
         h = hashlib.sha256(fh.read()).hexdigest()
-    rec = {"kernel": "k_syrk<float, Tile<64,64,2,2>> (Schur update, FP32+refine path)", "workload": workload,
+    rec = {"kernel": "k_syrk<float, Tile<64,64,2,2,16>> (trailing Schur update, FP32+refine path)", "workload": workload,
            "schur_tile_by_front_size": tiles, "launches": n,
            "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
            "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
