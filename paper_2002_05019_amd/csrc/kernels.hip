@@ -793,7 +793,11 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64K32> sm;
-  __shared__ T wr[GT][GT + 1], wi[GT][GT + 1];
+  // W staging reuses the GEMM's LDS once the product is done (half the LDS
+  // of the kernel, so its workgroups find room beside the side stream's)
+  static_assert(2 * GT * (GT + 1) * sizeof(T) <= sizeof(GemmSmem<T, T64K32>), "W staging in the GEMM LDS");
+  T(*wr)[GT + 1] = reinterpret_cast<T(*)[GT + 1]>(&sm.a[0][0][0]);
+  T(*wi)[GT + 1] = wr + GT;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int k = it.k, r0 = it.i, n = f.n, b = min(NB, f.s - k);
@@ -821,6 +825,7 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
   };
   typename V4<T>::t cr[2][2], ci[2][2];
   gemm_tile<T, T64K32, false, false, 4>(sm, 0, b, fa, fb, cr, ci);
+  __syncthreads();   // every wave is done reading the GEMM's LDS
   // W buffer of the outer block starting at k - it.j
   T *Wr = p.num + f.woff + (((k - it.j) / KBLK) & 1) * f.wstride;
   T *Wi = Wr + (int64_t)n * f.wcols;
