@@ -960,8 +960,9 @@ __device__ __forceinline__ void zval(const T *fr, const T *fi, int n, int r, int
 //   T1  = L_true(second half rows, first half cols) Z11   -> upper triangle (transposed)
 //   Z21 = -Z22 T1                                         -> lower triangle
 // Item (f, m0, r0, c0): output tile rows [r0, r0+64), columns [c0, c0+64).
+// three waves per SIMD (no spills at that register budget)
 template <typename T>
-__global__ __launch_bounds__(256) void k_zrec1(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -998,8 +999,9 @@ __global__ __launch_bounds__(256) void k_zrec1(KP<T> p, int64_t first) {
       }
 }
 
+// three waves per SIMD (no spills at that register budget)
 template <typename T>
-__global__ __launch_bounds__(256) void k_zrec2(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256, 3) void k_zrec2(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -1805,8 +1807,9 @@ __device__ __forceinline__ void zslot_out(const typename V4<T>::t (&cr)[2][2], c
 }
 
 // M = 0, 1: A(o, k) is a row block of the front (contiguous along o)
+// three waves per SIMD (no spills at that register budget)
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_zmma_n(KP<T> p, int64_t first, int nrhs) {
+__global__ __launch_bounds__(256, 3) void k_zmma_n(KP<T> p, int64_t first, int nrhs) {
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
