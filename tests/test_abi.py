@@ -150,9 +150,11 @@ def test_symbolic_structure_of_cube_cases():
 
 def test_interior_domain_flops_match_appendix_model():
     """A 12^3 interior domain: interior elimination plus the interface
-    Schur inverse; the survey's calibrated nested-dissection model gives
-    ~8.0e8 complex FMAs for the interior part and g^3/2 for the interface
-    (g = 1728).  Our own ordering must land within 25% of that."""
+    Schur inverse.  A geometric nested-dissection front model (recursive
+    longest-side bisection, leaves of at most 2 elements per side, calibrated
+    against an exact symbolic factorisation of the 12^3 domain) gives ~8.0e8
+    complex FMAs for the interior part, and the interface inverse costs
+    g^3/2 (g = 1728).  Our own ordering must land within 25% of that."""
     c = cached_case("cube48")
     s = B.Solver.from_case(c)
     dom = 21                                       # an interior domain of the 4x4x4 grid
