@@ -868,10 +868,11 @@ __global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
 // Trailing update (q0 >= block end): lower tiles of the trailing matrix,
 // kend = min(k + KBLK, s).  Column update (q0 < block end): the pivot tile
 // column starting at q0 receives the block's earlier tiles, kend = q0.
-// 64-edge tiles ask for three waves per SIMD (the FP64 instantiation would
-// otherwise take two: 204 registers)
+// 64-edge tiles ask for four waves per SIMD (the FP64 instantiation would
+// otherwise take two: 204 registers; at 128 it keeps one 8-byte value in
+// scratch, reloaded only on the ragged-tail path)
 template <typename T, class TL>
-__global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 3 : 1) void k_syrk(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, TL> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
