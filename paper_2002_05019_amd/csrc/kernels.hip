@@ -334,24 +334,45 @@ __global__ __launch_bounds__(256) void k_asm(KP<T> p, int64_t first) {
         coff[ch] = cf.off + cf.s + (int64_t)cf.s * cf.n;   // origin of the update block
       }
     }
-    for (int c = c0; c < cend && c <= r; ++c) {
-      T vr = 0, vi = 0;
+    // four columns per step; the loads are unconditional (a non-contributing
+    // entry reads the child's update-block origin) and selected afterwards,
+    // so all of a step's loads are in flight together
+    const int cstop = min(cend, r + 1);
+    for (int cb = c0; cb < cstop; cb += 4) {
+      T vr[4] = {0, 0, 0, 0}, vi[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int ch = 0; ch < 8; ++ch) {
-        const int rc = rmc[ch][c - c0];
-        if (rr[ch] >= 0 && rc >= 0) {
-          const int64_t o = coff[ch] + rr[ch] + rc * cn[ch];
-          vr += p.num[o];
-          vi += p.num[o + cplane[ch]];
+        if (ch >= ng) break;   // uniform
+        T xr[4], xi[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = cb + u;
+          const int rcv = rmc[ch][min(c, cstop - 1) - c0];
+          const int rc = c < cstop ? rcv : -1;
+          ok[u] = rr[ch] >= 0 && rc >= 0;
+          const int64_t o = coff[ch] + (ok[u] ? rr[ch] + rc * cn[ch] : 0);
+          xr[u] = p.num[o];
+          xi[u] = p.num[o + cplane[ch]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          vr[u] += ok[u] ? xr[u] : T(0);
+          vi[u] += ok[u] ? xi[u] : T(0);
         }
       }
-      const int64_t o = r + (int64_t)c * n;
-      if (g0 == 0) {
-        re[o] = vr;
-        im[o] = vi;
-      } else {
-        re[o] += vr;
-        im[o] += vi;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = cb + u;
+        if (c >= cstop) break;
+        const int64_t o = r + (int64_t)c * n;
+        if (g0 == 0) {
+          re[o] = vr[u];
+          im[o] = vi[u];
+        } else {
+          re[o] += vr[u];
+          im[o] += vi[u];
+        }
       }
     }
   }
