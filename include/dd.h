@@ -182,6 +182,20 @@ dd_status dd_factor(dd_ctx ctx, const dd_z *vals, void *hip_stream);
 dd_status dd_solve(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u,
                    int64_t ldu, dd_z *lam, int64_t ldl, void *hip_stream);
 
+/* Solve with recovery of a subset of the primal unknowns (section II: after
+ * the multipliers, the primal unknowns of all domains or of only some are
+ * recovered by independent substitutions).  Same arguments and layouts as
+ * dd_solve without the multipliers; domain_mask is a host array of n_dom
+ * bytes.  The condensation and the auxiliary solve involve every domain;
+ * only the domains with domain_mask[i] != 0 are back-substituted, and only
+ * their rows of u are written (the other rows are left unchanged).  Those
+ * rows equal dd_solve's bit for bit.  The mask is copied during the call
+ * (stream-ordered).  FP64 contexts only: refinement needs every domain's
+ * solution (DD_ERR_ARG for FP32_REFINE).
+ * Errors: DD_ERR_ARG, DD_ERR_STATE (not factored), DD_ERR_DEVICE. */
+dd_status dd_solve_subset(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, int64_t ldu,
+                          const uint8_t *domain_mask, void *hip_stream);
+
 /* Statistics; synchronises the streams of the last factor/solve. */
 dd_status dd_get_info(dd_ctx ctx, dd_info *info);
 

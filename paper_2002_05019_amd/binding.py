@@ -50,7 +50,7 @@ class dd_info(C.Structure):
 
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
            "dd_solve", "dd_get_info", "dd_get_interface_dofs", "dd_get_interface_inverse",
-           "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_tune",
+           "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_tune", "dd_solve_subset",
            "dd_destroy", "dd_last_error"]
 TILE_BUCKETS = 5   # front sizes [0,512) [512,1024) [1024,2048) [2048,4096) [4096,...)
 KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3, "column_update": 4}
@@ -74,6 +74,7 @@ def load():
     lib.dd_bind_workspace.argtypes = [vp, vp, C.c_int64]
     lib.dd_factor.argtypes = [vp, vp, vp]
     lib.dd_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp, C.c_int64, vp]
+    lib.dd_solve_subset.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, _P(C.c_uint8), vp]
     lib.dd_get_info.argtypes = [vp, _P(dd_info)]
     lib.dd_get_interface_dofs.argtypes = [vp, C.c_int32, _P(C.c_int32), _P(C.c_int32)]
     lib.dd_get_interface_inverse.argtypes = [vp, C.c_int32, vp, vp]
@@ -225,6 +226,27 @@ class Solver:
         if return_lam:
             return u, lam.t()
         return u
+
+    def solve_subset(self, f, domains, u=None, stream=None):
+        """Recovers the primal unknowns of the listed domains only (FP64
+        contexts).  f: complex128 device tensor (n_torn, nrhs); u: optional
+        output of the same shape whose other rows are left as they are
+        (zeros when u is None).  Returns u."""
+        import torch
+        F = f.reshape(self.n_torn, -1)
+        nrhs = F.shape[1]
+        fc = F.t().contiguous()
+        uc = torch.zeros_like(fc) if u is None else u.reshape(self.n_torn, -1).t().contiguous()
+        mask = np.zeros(self.n_dom, dtype=np.uint8)
+        mask[np.asarray(list(domains), dtype=np.int64)] = 1
+        st = self._lib.dd_solve_subset(self._ctx, nrhs, C.c_void_p(fc.data_ptr()), self.n_torn,
+                                       C.c_void_p(uc.data_ptr()), self.n_torn, _ptr(mask, C.c_uint8),
+                                       self._stream(stream))
+        self.last_status = st
+        _check(st)
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        out = uc.t()
+        return out.reshape(-1) if f.dim() == 1 else out
 
     def info(self):
         inf = dd_info()

@@ -85,13 +85,14 @@ hipError_t capture(dd_ctx_s *c, F enqueue, hipGraphExec_t *out) {
   return e;
 }
 
-hipError_t run_solve_core(dd_ctx_s *c, int nrhs, bool with_c, hipStream_t st) {
-  if (!c->opt.use_graph) return dd::solve_core(c->plan, c->ws, nrhs, with_c, st);
-  auto key = std::make_pair(nrhs, with_c ? 1 : 0);
+hipError_t run_solve_core(dd_ctx_s *c, int nrhs, bool with_c, hipStream_t st, bool subset = false) {
+  if (!c->opt.use_graph) return dd::solve_core(c->plan, c->ws, nrhs, with_c, st, nullptr, subset);
+  auto key = std::make_pair(nrhs, (with_c ? 1 : 0) + (subset ? 2 : 0));
   auto it = c->gsolve.find(key);
   if (it == c->gsolve.end()) {
     hipGraphExec_t ge;
-    hipError_t e = capture(c, [&](hipStream_t s) { return dd::solve_core(c->plan, c->ws, nrhs, with_c, s); }, &ge);
+    hipError_t e = capture(
+        c, [&](hipStream_t s) { return dd::solve_core(c->plan, c->ws, nrhs, with_c, s, nullptr, subset); }, &ge);
     if (e != hipSuccess) return e;
     it = c->gsolve.emplace(key, ge).first;
   }
@@ -340,6 +341,40 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
   HIPCHECK(hipEventRecord(c->ev[3], st));
   c->solve_rec = true;
   return result;
+}
+
+dd_status dd_solve_subset(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, int64_t ldu,
+                          const uint8_t *domain_mask, void *stream) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  const dd::Plan &P = c->plan;
+  if (P.precision != 0)
+    return fail(DD_ERR_ARG, "subset recovery needs the FP64 path (refinement uses every domain's solution)");
+  if (nrhs < 0) return fail(DD_ERR_ARG, "nrhs < 0");
+  if (!domain_mask) return fail(DD_ERR_ARG, "domain_mask is null");
+  if (!c->factored) return fail(DD_ERR_STATE, "dd_solve_subset before dd_factor");
+  if (nrhs == 0) return DD_OK;
+  if (!f || !u) return fail(DD_ERR_ARG, "f or u is null");
+  if (ldf < P.n_torn || ldu < P.n_torn) return fail(DD_ERR_ARG, "leading dimension below the torn size");
+  if ((const void *)f == (const void *)u) return fail(DD_ERR_ARG, "u may not alias f");
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    c->last = st;
+    HIPCHECK(hipMemcpyAsync(c->ws + P.b_dmask, domain_mask, (size_t)P.n_dom, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipEventRecord(c->ev[2], st));
+    c->refine_iters = 0;
+    c->rel_resid = 0;
+    for (int32_t j0 = 0; j0 < nrhs; j0 += P.max_rhs) {
+      const int nb = std::min<int32_t>(P.max_rhs, nrhs - j0);
+      HIPCHECK(dd::rhs_in(P, c->ws, f + (int64_t)j0 * ldf, ldf, nb, st));
+      HIPCHECK(run_solve_core(c, nb, false, st, true));
+      HIPCHECK(dd::sol_out(P, c->ws, u + (int64_t)j0 * ldu, ldu, nullptr, 0, nb, st, true));
+    }
+    HIPCHECK(hipEventRecord(c->ev[3], st));
+    c->solve_rec = true;
+  } catch (...) {
+    return fail(DD_ERR_DEVICE, "unexpected exception");
+  }
+  return DD_OK;
 }
 
 dd_status dd_get_info(dd_ctx c, dd_info *info) {

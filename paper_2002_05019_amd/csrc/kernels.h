@@ -16,11 +16,15 @@ hipError_t factor(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st, 
 hipError_t run_launch(const Plan &P, uint8_t *ws, const Launch &L, hipStream_t st);
 // torn right-hand sides (interleaved complex FP64, ld ldf) -> internal vector
 hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, hipStream_t st);
-// one DD solve of the internal right-hand side (with_c: constraint rhs in vc)
-hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm = nullptr);
-// internal solution / multipliers -> interleaved complex FP64
+// one DD solve of the internal right-hand side (with_c: constraint rhs in vc;
+// subset: the backward substitution skips the domains whose byte in the
+// workspace's domain mask is 0)
+hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm = nullptr,
+                      bool subset = false);
+// internal solution / multipliers -> interleaved complex FP64 (subset: only
+// the rows of the domains selected in the domain mask)
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
-                   hipStream_t st);
+                   hipStream_t st, bool subset = false);
 hipError_t interface_inverse_out(const Plan &P, uint8_t *ws, int front, void *out, hipStream_t st);
 // FP64 iterative refinement around the FP32 factorisation
 // FP64 copy of the operator values (caller's CSR order) into the workspace's

@@ -47,6 +47,10 @@ struct KP {
   const int64_t *csrp;
   const int64_t *sellp;
   const int32_t *sellc;
+  const int64_t *domrow;
+  // subset solve: domains whose mask byte is 0 skip the backward
+  // substitution (null: every domain)
+  const uint8_t *dmask;
   const Item *gemv;
   T *num;
   cd *dinv;
@@ -58,7 +62,7 @@ struct KP {
   double *r64;
   int64_t vf, vx, vd, vl, vc, part;
   int64_t n_torn, n_mult;
-  int32_t mr;
+  int32_t mr, n_dom;
 };
 
 // ---------------------------------------------------------------------------
@@ -1121,6 +1125,12 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
       }
 }
 
+// subset solve: is front f's domain left out of the backward substitution?
+template <typename T>
+__device__ __forceinline__ bool skipped(const KP<T> &p, const FrontDev &f) {
+  return p.dmask && f.dom >= 0 && !p.dmask[f.dom];
+}
+
 // ---------------------------------------------------------------------------
 // multi-RHS substitutions (front vectors v: n x mr planar, ld n)
 // Front vector rows [it.i, it.i + 256): gathered right-hand side on the
@@ -1246,6 +1256,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs) {
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
+  if (skipped(p, f)) return;
   const int n = f.n, r = it.i + threadIdx.x;
   if (r >= n) return;
   const int64_t mr = p.mr;
@@ -1279,6 +1290,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) {
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
+  if (skipped(p, f)) return;
   const int n = f.n, r = it.i + threadIdx.x;
   if (r >= f.s) return;
   const int64_t mr = p.mr;
@@ -1563,6 +1575,7 @@ __global__ __launch_bounds__(256) void k_ffront(KP<T> p, int64_t first, int nrhs
 // (z_k - L21^T x_below), finally the fully-summed part is scattered.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bfront(KP<T> p, int64_t first, int nrhs) {
+  if (skipped(p, p.F[p.items[first + blockIdx.x].f])) return;
   __shared__ T lr[64][NB + 1], li[64][NB + 1];
   __shared__ T xr[64][17], xi[64][17];
   __shared__ T zr[NB][17], zi[NB][17];
@@ -1753,6 +1766,7 @@ __global__ __launch_bounds__(256) void k_zq_t(KP<T> p, int64_t first, int nrhs) 
   __shared__ __align__(16) T xs[64 * 16];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
+  if (skipped(p, f)) return;
   const int n = f.n, s = f.s, i0 = it.i, k0 = it.j, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int kend = min(k0 + ZKC, M == 2 ? n : s);
   const int64_t mr = p.mr;
@@ -1878,6 +1892,7 @@ __global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
+  if (skipped(p, f)) return;
   const int n = f.n, s = f.s, i0 = it.i, k0 = it.j;
   const int kend = min(k0 + ZKC, M == 2 ? n : s);
   const int64_t mr = p.mr;
@@ -1917,6 +1932,7 @@ template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) {
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
+  if (M >= 2 && skipped(p, f)) return;   // backward reductions only
   const int n = f.n, s = f.s;
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
@@ -1954,6 +1970,7 @@ __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) 
 // blocks of the right-hand sides over the full inner dimension g
 template <typename T>
 __global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
+  if (mode == 1 && skipped(p, p.F[p.gemv[blockIdx.x].f])) return;
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.gemv[blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -2009,6 +2026,7 @@ __global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
 // 256 columns of X at a time
 template <typename T>
 __global__ __launch_bounds__(256) void k_xq(KP<T> p, int mode, int nrhs) {
+  if (mode == 1 && skipped(p, p.F[p.gemv[blockIdx.x].f])) return;
   __shared__ __align__(16) T xs[256 * 16];
   const Item it = p.gemv[blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -2139,6 +2157,16 @@ __global__ void k_t2u(KP<T> p, cd *u, int64_t ldu, int nrhs, int which) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= rows * nrhs) return;
   const int64_t r = e % rows, j = e / rows;
+  if (!which && p.dmask) {
+    // domain of torn row r (rows are contiguous per domain)
+    int lo = 0, hi = p.n_dom;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (p.domrow[mid] <= r) lo = mid;
+      else hi = mid;
+    }
+    if (!p.dmask[lo]) return;
+  }
   const T *s = p.num + (which ? p.vl : p.vx);
   u[r + j * ldu] = cd{(double)s[r + j * rows], (double)s[r + j * rows + rows * p.mr]};
 }
@@ -2371,6 +2399,8 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
   k.csrp = (const int64_t *)(m + P.m_csrp);
   k.sellp = (const int64_t *)(m + P.m_sellp);
   k.sellc = (const int32_t *)(m + P.m_sellc);
+  k.domrow = (const int64_t *)(m + P.m_domrow);
+  k.dmask = nullptr;
   k.gemv = (const Item *)(m + P.m_gemv);
   k.num = (T *)(ws + P.b_num);
   uint8_t *sd = ws + P.b_side;
@@ -2390,6 +2420,7 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
   k.n_torn = P.n_torn;
   k.n_mult = P.n_mult;
   k.mr = P.max_rhs;
+  k.n_dom = P.n_dom;
   return k;
 }
 
@@ -2481,8 +2512,10 @@ static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStre
 }
 
 template <typename T>
-static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm) {
+static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm,
+                               bool subset) {
   KP<T> k = make_kp<T>(P, ws, nullptr);
+  if (subset) k.dmask = ws + P.b_dmask;
   hipError_t e = run_seq<T>(P, k, P.solve_dom_fwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   if (!P.gemv_items.empty())
@@ -2523,15 +2556,16 @@ hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nr
   return hipGetLastError();
 }
 
-hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm) {
-  return P.precision == 0 ? solve_core_t<double>(P, ws, nrhs, with_c, st, tm)
-                          : solve_core_t<float>(P, ws, nrhs, with_c, st, tm);
+hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm, bool subset) {
+  return P.precision == 0 ? solve_core_t<double>(P, ws, nrhs, with_c, st, tm, subset)
+                          : solve_core_t<float>(P, ws, nrhs, with_c, st, tm, subset);
 }
 
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
-                   hipStream_t st) {
+                   hipStream_t st, bool subset) {
   if (P.precision == 0) {
     KP<double> k = make_kp<double>(P, ws, nullptr);
+    if (subset) k.dmask = ws + P.b_dmask;
     hipLaunchKernelGGL(k_t2u<double>, dim3(nblk(P.n_torn * nrhs)), dim3(256), 0, st, k, (cd *)u, ldu, nrhs, 0);
     if (lam && P.n_mult)
       hipLaunchKernelGGL(k_t2u<double>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, (cd *)lam, ldl, nrhs, 1);

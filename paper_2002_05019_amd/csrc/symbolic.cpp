@@ -1303,6 +1303,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.m_csrp = put(P.csr_ptr.data(), P.csr_ptr.size() * 8);
   P.m_sellp = put(P.sell_ptr.data(), P.sell_ptr.size() * 8);
   P.m_sellc = put(P.sell_col.data(), P.sell_col.size() * 4);
+  P.m_domrow = put(P.dom_row.data(), P.dom_row.size() * 8);
 
   // ------------------------------------------------------------ workspace (bytes)
   auto A256 = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
@@ -1326,6 +1327,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     b = A256(b + r * 8);
   }
   P.b_status = b; b = A256(b + 256);
+  P.b_dmask = b; b = A256(b + std::max(1, p.n_dom));   // domain mask of the subset solve
   P.b_total = b;
 
   if (o.verbose) {

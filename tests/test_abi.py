@@ -116,6 +116,15 @@ def test_option_and_state_errors():
     assert lib.dd_factor(ctx, z, None) == -4          # no workspace bound
     assert lib.dd_solve(ctx, 1, z, 4, z, 4, None, 0, None) == -4   # before factor
     assert lib.dd_bind_workspace(ctx, C.c_void_p(256), 1) == -5    # too small
+    mask = (C.c_uint8 * 1)(1)
+    assert lib.dd_solve_subset(ctx, 1, z, 4, z, 4, None, None) == -1   # no mask
+    assert lib.dd_solve_subset(ctx, 1, z, 4, z, 4, mask, None) == -4   # before factor
+    lib.dd_destroy(ctx)
+    lib.dd_default_options(C.byref(opt))
+    opt.precision = 1
+    st, ctx, lib = _problem([rp], [ci], opt=C.byref(opt))
+    assert st == 0
+    assert lib.dd_solve_subset(ctx, 1, z, 4, z, 4, mask, None) == -1   # FP64 contexts only
     lib.dd_destroy(ctx)
 
 

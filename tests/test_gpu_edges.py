@@ -82,3 +82,28 @@ def test_full_size_sampled_parity():
     um = um.cpu().numpy()
     assert oracle.global_residual(c, um).max() < 1e-8
     assert _colerr(um, u64) < 1e-7
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_subset_recovery_matches_full_solve(graph):
+    """Section II: after the multipliers, the primal unknowns of only some
+    domains are recovered.  The selected domains' rows equal the full solve
+    bit for bit (same arithmetic); the other rows are left untouched."""
+    c = cached_case("cube18u")
+    print(f"[parity] subset recovery cube18u graph={graph}", flush=True)
+    s = _solver(c, use_graph=graph)
+    f = _rhs(c)
+    full = s.solve(f).cpu().numpy()
+    offs = np.cumsum([0] + [d.n for d in c.domains])
+    pick = [0, 3, c.n_dom - 1]
+    sentinel = torch.full_like(f, 7.0 + 7.0j)
+    for rep in range(2):
+        u = s.solve_subset(f, pick, u=sentinel).cpu().numpy()
+        for i in range(c.n_dom):
+            rows = slice(offs[i], offs[i + 1])
+            if i in pick:
+                assert np.array_equal(u[rows], full[rows]), (rep, i)
+            else:
+                assert np.all(u[rows] == 7.0 + 7.0j), (rep, i)
+    # the full solve still works after subset solves
+    assert np.array_equal(s.solve(f).cpu().numpy(), full)
