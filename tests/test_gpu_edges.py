@@ -107,3 +107,23 @@ def test_subset_recovery_matches_full_solve(graph):
                 assert np.all(u[rows] == 7.0 + 7.0j), (rep, i)
     # the full solve still works after subset solves
     assert np.array_equal(s.solve(f).cpu().numpy(), full)
+
+
+def test_frequency_sweep_reuses_the_symbolic_phase():
+    """Many excitations over a frequency sweep: one context (one symbolic
+    phase, one workspace) refactored at three wavenumbers; every solution
+    against the oracle of its own operator."""
+    base = cached_case("cube12")
+    s = None
+    for scale in (1.0, 0.8, 1.25):
+        c = cached_case("cube12", k0=base.spec.k0 * scale)
+        print(f"[parity] frequency sweep cube12 k0 x {scale}", flush=True)
+        if s is None:
+            s = _solver(c)
+        else:
+            assert all(np.array_equal(a.K.indptr, b.K.indptr) and np.array_equal(a.K.indices, b.K.indices)
+                       for a, b in zip(c.domains, base.domains))
+            s.factor(torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV))
+        u = s.solve(_rhs(c))
+        torch.cuda.synchronize()
+        assert _colerr(u.cpu().numpy(), oracle.serial_dd(c)["u"]) < 1e-10
