@@ -28,9 +28,6 @@ enum LaunchKind : int32_t {
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)
-  S_GEMV,       // interface: out = a*X*in + add
-  S_MGATHER,    // d = sum_i B_i y_i - c
-  S_HGATHER,    // h = B_Gamma^T lambda
   S_BINIT,      // update rows of the front vector from the global solution
   S_BFIN,       // fully-summed rows of the front vector to the global solution
   S_FFRONT,     // whole-front forward substitution, one workgroup per front
