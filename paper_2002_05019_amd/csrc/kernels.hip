@@ -165,19 +165,28 @@ __device__ __forceinline__ void col4(const T *pr, const T *pi, int x0, int lim, 
 // The next K chunk is fetched into registers while the current one is
 // multiplied.  With VW = 4 (operands contiguous along m only) each thread
 // fetches four consecutive m of one k: fa(m0, k, re[4], im[4]).
-template <typename T, class TL, bool AK, bool BK, int VW = 1, class FA, class FB>
+// G3 selects Gauss's three-product form of the complex product (Higham,
+// "Stability of a method for multiplying complex matrices with three real
+// matrix multiplications", SIMAX 1992): T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2, Im = T3 - T1 - T2.  It takes three
+// matrix-core products per step instead of four and is stable normwise, not
+// componentwise (the imaginary part can lose relative accuracy where it is
+// small against |A||B|).
+template <typename T, class TL, bool AK, bool BK, int VW = 1, bool G3 = false, class FA, class FB>
 __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int kend, FA fa, FB fb,
                                           typename V4<T>::t (&cr)[TL::XB][TL::YB],
                                           typename V4<T>::t (&ci)[TL::XB][TL::YB]) {
   constexpr int NTH = TL::NTH, XB = TL::XB, YB = TL::YB, RA = TL::REPA, RB = TL::REPB, TK = TL::TK;
   static_assert(VW == 1 || (VW == 4 && !AK && !BK && RA % 4 == 0 && RB % 4 == 0), "vector fetch layout");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w / TL::WC, wc = w % TL::WC;
+  typename V4<T>::t ct[XB][YB];   // T3 of the three-product form
 #pragma unroll
   for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < YB; ++y) {
       cr[x][y] = typename V4<T>::t{0, 0, 0, 0};
       ci[x][y] = typename V4<T>::t{0, 0, 0, 0};
+      ct[x][y] = typename V4<T>::t{0, 0, 0, 0};
     }
   // operand element `rep` of this thread: along k (contiguous) TK threads
   // cover one K chunk; otherwise BM (BN) threads cover one k
@@ -279,16 +288,42 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
         br[y] = sm.b[0][kr][wc * YB * 16 + y * 16 + (lane & 15)];
         bi[y] = sm.b[1][kr][wc * YB * 16 + y * 16 + (lane & 15)];
       }
+      if constexpr (G3) {
+        T as[XB], bs[YB];
 #pragma unroll
-      for (int x = 0; x < XB; ++x)
+        for (int x = 0; x < XB; ++x) as[x] = ar[x] + ai[x];
 #pragma unroll
-        for (int y = 0; y < YB; ++y) {
-          cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
-          cr[x][y] = mfma16(-bi[y], ai[x], cr[x][y]);
-          ci[x][y] = mfma16(bi[y], ar[x], ci[x][y]);
-          ci[x][y] = mfma16(br[y], ai[x], ci[x][y]);
-        }
+        for (int y = 0; y < YB; ++y) bs[y] = br[y] + bi[y];
+#pragma unroll
+        for (int x = 0; x < XB; ++x)
+#pragma unroll
+          for (int y = 0; y < YB; ++y) {
+            cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
+            ci[x][y] = mfma16(bi[y], ai[x], ci[x][y]);
+            ct[x][y] = mfma16(bs[y], as[x], ct[x][y]);
+          }
+      } else {
+#pragma unroll
+        for (int x = 0; x < XB; ++x)
+#pragma unroll
+          for (int y = 0; y < YB; ++y) {
+            cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
+            cr[x][y] = mfma16(-bi[y], ai[x], cr[x][y]);
+            ci[x][y] = mfma16(bi[y], ar[x], ci[x][y]);
+            ci[x][y] = mfma16(br[y], ai[x], ci[x][y]);
+          }
+      }
     }
+  }
+  if constexpr (G3) {
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int y = 0; y < YB; ++y) {
+        const typename V4<T>::t t1 = cr[x][y], t2 = ci[x][y];
+        cr[x][y] = t1 - t2;
+        ci[x][y] = (ct[x][y] - t1) - t2;
+      }
   }
 }
 
@@ -946,7 +981,12 @@ __global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p,
     }
   };
   typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
-  gemm_tile<T, TL, false, false, 4>(sm, k, kend, fa, fb, cr, ci);
+  // FP32 (the refined path): the three-product form.  FP64 keeps four
+  // products: a third accumulator set does not fit its register budget, and
+  // the FP64 path is the accuracy reference.  Only this update uses it: in
+  // the interface inverses and the panel solve it moved the refined solution's
+  // global residual measurably for little time saved.
+  gemm_tile<T, TL, false, false, 4, sizeof(T) == 4>(sm, k, kend, fa, fb, cr, ci);
   const bool diag = (r0 == q0);
 #pragma unroll
   for (int x = 0; x < TL::XB; ++x)
