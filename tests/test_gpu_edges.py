@@ -84,6 +84,35 @@ def test_full_size_sampled_parity():
     assert _colerr(um, u64) < 1e-7
 
 
+def test_full_size_reciprocity_and_linearity():
+    """Properties of A^-1 that hold at any size, on the 48^3 bench workload in
+    the timed configuration (tuned tiles, graph replay, FP64).  Reciprocity:
+    A is complex symmetric, so u_j^T f_i = u_i^T f_j (no conjugation); with the
+    torn convention f is nonzero only on owner copies, where u is the global
+    value, so the torn products are the global ones.  Linearity: the solve
+    of F C equals U C for a fixed complex 8 x 8 C.  Each solution is within
+    1e-10 of A^-1 f per column (the FP64 gate), so both identities hold to
+    2e-10 relative."""
+    c = cached_case("cube48")
+    print("[parity] cube48 full size: reciprocity and linearity (fp64, tuned, graph)", flush=True)
+    f = _rhs(c)
+    s = _solver(c, max_rhs=8, use_graph=True)
+    s.tune()
+    s.factor(torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV))
+    U = s.solve(f).cpu().numpy()
+    F = f.cpu().numpy()
+    M = U.T @ F
+    scale = np.linalg.norm(U, axis=0).max() * np.linalg.norm(F, axis=0).max()
+    rec = np.abs(M - M.T).max() / scale
+    rng = np.random.default_rng(4805)
+    C = (rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))) / 4
+    UC = s.solve(torch.from_numpy(np.ascontiguousarray(F @ C)).to(DEV)).cpu().numpy()
+    lin = _colerr(UC, U @ C)
+    print(f"[parity] cube48 reciprocity {rec:.2e} linearity {lin:.2e}", flush=True)
+    assert rec < 2e-10, rec
+    assert lin < 2e-10, lin
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_subset_recovery_matches_full_solve(graph):
     """Section II: after the multipliers, the primal unknowns of only some
