@@ -1106,7 +1106,64 @@ __global__ __launch_bounds__(256, 3) void k_zrec2(KP<T> p, int64_t first) {
       }
 }
 
-// X(P a, P c) = sum_r Z(r, a) (D^-1 Z)(r, c), lower tiles, written to both triangles
+// Y = D^-1 Z of an interface root: the 1 x 1 and 2 x 2 pivots applied to the
+// rows of Z = L^-1 (FP64 arithmetic, rounded to the front type).  Once Z is
+// complete the front's diagonal and upper triangle are free (Z is unit lower,
+// D is kept apart), so Y is stored there transposed: Y(r, c), r >= c, at
+// position (c, r).  The only entries of Y above its diagonal, Y(r - 1, r) of
+// a 2 x 2 pivot (r - 1, r), equal its off-diagonal D^-1 entry and are not
+// stored.  Item (f, 0, r0, c0), r0 >= c0: the 64 x 64 tile rows
+// [r0, r0 + 64) x columns [c0, c0 + 64) of Y, transposed through LDS so that
+// both the reads of Z and the writes of Y^T run along contiguous rows.  Reads
+// touch only the strict lower triangle and writes only the rest, so the
+// tiles are independent.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dinvz(KP<T> p, int64_t first) {
+  __shared__ T yr_[64][65], yi_[64][65];
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, r0 = it.i, c0 = it.j, tid = threadIdx.x;
+  T *fr = p.num + f.off;
+  T *fi = fr + (int64_t)n * n;
+  const cd *dv = p.dinv + f.soff;
+  const cd *dof = p.doff + f.soff;
+  const int32_t *pd = p.pdel + f.soff;
+#pragma unroll 4
+  for (int u = 0; u < 16; ++u) {
+    const int rr = tid & 63, cc = (tid >> 6) + 4 * u, r = r0 + rr, c = c0 + cc;
+    double xr = 0, xi = 0;
+    if (r < n && c < n && r >= c) {
+      T zr = 0, zi = 0;
+      zval(fr, fi, n, r, c, zr, zi);
+      const cd d = dv[r];
+      xr = d.re * (double)zr - d.im * (double)zi;
+      xi = d.re * (double)zi + d.im * (double)zr;
+      const int q = pd[r];
+      if (q) {
+        T wr = 0, wi = 0;
+        zval(fr, fi, n, r + q, c, wr, wi);
+        const cd o = dof[r];
+        xr += o.re * (double)wr - o.im * (double)wi;
+        xi += o.re * (double)wi + o.im * (double)wr;
+      }
+    }
+    yr_[cc][rr] = (T)xr;
+    yi_[cc][rr] = (T)xi;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int u = 0; u < 16; ++u) {
+    const int cc = tid & 63, rr = (tid >> 6) + 4 * u, r = r0 + rr, c = c0 + cc;
+    if (r < n && c < n && r >= c) {
+      const int64_t o = c + (int64_t)r * n;
+      fr[o] = yr_[cc][rr];
+      fi[o] = yi_[cc][rr];
+    }
+  }
+}
+
+// X(P a, P c) = sum_r Z(r, a) Y(r, c), Y = D^-1 Z as stored by k_dinvz;
+// lower tiles, written to both triangles
 template <typename T>
 __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
@@ -1115,7 +1172,6 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
   const int a0 = it.i, c0 = it.j, n = f.n;
   const T *fr = p.num + f.off;
   const T *fi = fr + (int64_t)n * n;
-  const cd *dv = p.dinv + f.soff;
   const cd *dof = p.doff + f.soff;
   const int32_t *pd = p.pdel + f.soff;
   const int32_t *pm = p.perm + f.soff;
@@ -1123,27 +1179,22 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
     const int a = a0 + m;
     if (a < n) zval(fr, fi, n, kk, a, re, im);
   };
+  // Y(kk, c0 + c): Y^T row c0 + c, contiguous along c
   auto fb = [&](int c, int kk, T &re, T &im) {
     const int cc = c0 + c;
     if (cc >= n) return;
-    T zr = 0, zi = 0;
-    zval(fr, fi, n, kk, cc, zr, zi);
-    const cd d = dv[kk];
-    double xr = d.re * (double)zr - d.im * (double)zi;
-    double xi = d.re * (double)zi + d.im * (double)zr;
-    const int q = pd[kk];
-    if (q) {
-      T wr = 0, wi = 0;
-      zval(fr, fi, n, kk + q, cc, wr, wi);
+    if (kk >= cc) {
+      const int64_t o = cc + (int64_t)kk * n;
+      re = fr[o];
+      im = fi[o];
+    } else if (kk == cc - 1 && pd[kk] == 1) {
       const cd o = dof[kk];
-      xr += o.re * (double)wr - o.im * (double)wi;
-      xi += o.re * (double)wi + o.im * (double)wr;
+      re = (T)o.re;
+      im = (T)o.im;
     }
-    re = (T)xr;
-    im = (T)xi;
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, true, true>(sm, a0, n, fa, fb, cr, ci);
+  gemm_tile<T, T64, true, false>(sm, a0, n, fa, fb, cr, ci);
   T *Xr = p.num + f.xoff;
   T *Xi = Xr + (int64_t)n * n;
   const bool diag = (a0 == c0);
@@ -2501,6 +2552,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_UPD: hipLaunchKernelGGL((k_syrk<T, T64K32>), g, b, 0, st, k, L.first); break;
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
+      case L_DINVZ: hipLaunchKernelGGL(k_dinvz<T>, g, b, 0, st, k, L.first); break;
       case L_INVSYRK: hipLaunchKernelGGL(k_invsyrk<T>, g, b, 0, st, k, L.first); break;
       case S_FINIT: hipLaunchKernelGGL(k_finit<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_FFIN: hipLaunchKernelGGL(k_ffin<T>, g, b, 0, st, k, L.first, nrhs); break;

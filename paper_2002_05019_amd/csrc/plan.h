@@ -20,11 +20,12 @@ enum LaunchKind : int32_t {
   L_SYRK,       // trailing update C -= L21 W^T
   L_ZREC1,      // recursive inverse: T1 = P L21 Z11 (upper triangle)
   L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
-  L_INVSYRK,    // X = P^T Z^T D^-1 Z P
+  L_INVSYRK,    // X = P^T Z^T Y P with Y = D^-1 Z
   L_SYRK2,      // trailing update on 128 x 128 tiles (512 threads)
   L_UPD,        // column update of a pivot tile by the outer block's earlier tiles (32-deep stages)
   L_FORK,       // the side stream waits for the main stream (no kernel)
   L_JOIN,       // the main stream waits for the side stream (no kernel)
+  L_DINVZ,      // Y = D^-1 Z of an interface root, stored transposed above Z
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)

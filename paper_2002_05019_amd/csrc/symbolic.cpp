@@ -1161,6 +1161,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       for (int ti = 0; ti < nt; ++ti)
         for (int tj = 0; tj <= ti; ++tj) sy.push_back({f, 0, ti * GT, tj * GT});
     }
+    push(P.factor_seq, L_DINVZ, sy);
     push(P.factor_seq, L_INVSYRK, sy);
   }
   for (auto &lv : aux_levels) {
