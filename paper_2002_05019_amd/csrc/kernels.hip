@@ -172,12 +172,14 @@ __device__ __forceinline__ void col4(const T *pr, const T *pi, int x0, int lim, 
 // matrix-core products per step instead of four and is stable normwise, not
 // componentwise (the imaginary part can lose relative accuracy where it is
 // small against |A||B|).
-template <typename T, class TL, bool AK, bool BK, int VW = 1, bool G3 = false, class FA, class FB>
+// VWB (default VW) sets the fetch width of the second operand on its own.
+template <typename T, class TL, bool AK, bool BK, int VW = 1, bool G3 = false, int VWB = VW, class FA, class FB>
 __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int kend, FA fa, FB fb,
                                           typename V4<T>::t (&cr)[TL::XB][TL::YB],
                                           typename V4<T>::t (&ci)[TL::XB][TL::YB]) {
   constexpr int NTH = TL::NTH, XB = TL::XB, YB = TL::YB, RA = TL::REPA, RB = TL::REPB, TK = TL::TK;
-  static_assert(VW == 1 || (VW == 4 && !AK && !BK && RA % 4 == 0 && RB % 4 == 0), "vector fetch layout");
+  static_assert(VW == 1 || (VW == 4 && !AK && RA % 4 == 0), "vector fetch layout (first operand)");
+  static_assert(VWB == 1 || (VWB == 4 && !BK && RB % 4 == 0), "vector fetch layout (second operand)");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w / TL::WC, wc = w % TL::WC;
   typename V4<T>::t ct[XB][YB];   // T3 of the three-product form
 #pragma unroll
@@ -213,6 +215,17 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
           ra[1][4 * g + e] = im[e];
         }
       }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < RA; ++rep) {
+        const int m = ma_(rep), k = ka_(rep);
+        T re = 0, im = 0;
+        if (k0 + k < kend) fa(m, k0 + k, re, im);
+        ra[0][rep] = re;
+        ra[1][rep] = im;
+      }
+    }
+    if constexpr (VWB == 4) {
 #pragma unroll
       for (int g = 0; g < RB / 4; ++g) {
         T re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
@@ -224,14 +237,6 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
         }
       }
     } else {
-#pragma unroll
-      for (int rep = 0; rep < RA; ++rep) {
-        const int m = ma_(rep), k = ka_(rep);
-        T re = 0, im = 0;
-        if (k0 + k < kend) fa(m, k0 + k, re, im);
-        ra[0][rep] = re;
-        ra[1][rep] = im;
-      }
 #pragma unroll
       for (int rep = 0; rep < RB; ++rep) {
         const int m = mb_(rep), k = kb_(rep);
@@ -253,6 +258,14 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
           sm.a[0][va_k(g)][va_m(g) + e] = ra[0][4 * g + e];
           sm.a[1][va_k(g)][va_m(g) + e] = ra[1][4 * g + e];
         }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < RA; ++rep) {
+        sm.a[0][ka_(rep)][ma_(rep)] = ra[0][rep];
+        sm.a[1][ka_(rep)][ma_(rep)] = ra[1][rep];
+      }
+    }
+    if constexpr (VWB == 4) {
 #pragma unroll
       for (int g = 0; g < RB / 4; ++g)
 #pragma unroll
@@ -261,11 +274,6 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, TL> &sm, int kbeg, int ken
           sm.b[1][vb_k(g)][vb_m(g) + e] = rb[1][4 * g + e];
         }
     } else {
-#pragma unroll
-      for (int rep = 0; rep < RA; ++rep) {
-        sm.a[0][ka_(rep)][ma_(rep)] = ra[0][rep];
-        sm.a[1][ka_(rep)][ma_(rep)] = ra[1][rep];
-      }
 #pragma unroll
       for (int rep = 0; rep < RB; ++rep) {
         sm.b[0][kb_(rep)][mb_(rep)] = rb[0][rep];
@@ -1026,30 +1034,34 @@ __device__ __forceinline__ void zval(const T *fr, const T *fi, int n, int r, int
 //   T1  = L_true(second half rows, first half cols) Z11   -> upper triangle (transposed)
 //   Z21 = -Z22 T1                                         -> lower triangle
 // Item (f, m0, r0, c0): output tile rows [r0, r0+64), columns [c0, c0+64).
+// The row block is one pivot tile (r0 is a multiple of the tile size): the
+// product runs over the stored rows (contiguous, 16-byte loads) and each
+// result row is written to its true row, found from the tile's permutation
+// inverted in LDS.
 // three waves per SIMD (no spills at that register budget)
 template <typename T>
 __global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
+  __shared__ int tr_of[NB];   // stored row r0 + i holds true row r0 + tr_of[i]
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int m0 = it.k, r0 = it.i, c0 = it.j, n = f.n, s = f.s;
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
   const int32_t *pm = p.perm + f.soff;
-  auto fa = [&](int m, int kk, T &re, T &im) {
-    const int r = r0 + m;
-    if (r < s) {
-      const int rs = (r / NB) * NB + pm[r];
-      const int64_t o = rs + (int64_t)kk * n;
-      re = fr[o];
-      im = fi[o];
-    }
+  static_assert(GT == NB, "row blocks are pivot tiles");
+  if (threadIdx.x < NB && r0 + (int)threadIdx.x < s) tr_of[pm[r0 + threadIdx.x]] = threadIdx.x;
+  // stored rows r0 + m .. + 3 of column kk (zero from s on)
+  auto fa = [&](int m, int kk, T (&re)[4], T (&im)[4]) {
+    const int64_t col = (int64_t)kk * n;
+    col4(fr + col, fi + col, r0 + m, s, re, im);
   };
   auto fb = [&](int c, int kk, T &re, T &im) {   // Z(kk, c0 + c)
     zval(fr, fi, n, kk, c0 + c, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, true>(sm, c0, m0, fa, fb, cr, ci);
+  gemm_tile<T, T64, false, true, 4, false, 1>(sm, c0, m0, fa, fb, cr, ci);
+  __syncthreads();   // tr_of complete (also for an empty K range)
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -1058,7 +1070,7 @@ __global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
       for (int i = 0; i < 4; ++i) {
         const int m = out_row(x), c = out_col<T>(y, i);
         if (r0 + m < s && c0 + c < m0) {
-          const int64_t o = (c0 + c) + (int64_t)(r0 + m) * n;
+          const int64_t o = (c0 + c) + (int64_t)(r0 + tr_of[m]) * n;
           fr[o] = cr[x][y][i];
           fi[o] = ci[x][y][i];
         }
