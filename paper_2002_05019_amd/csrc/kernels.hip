@@ -530,6 +530,10 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
   // NT threads: rows tr + 16u (u < 4), columns tc + TC v (v < CV)
   constexpr int TC = NT / 16, CV = NB / TC, NW = NT / 64;
   static_assert(NT == 256 || NT == 512 || NT == 1024, "tile thread grid");
+  // owner column group and register slot of a (non-negative) tile index:
+  // unsigned, so they compile to a mask and a shift
+  auto qc = [](int q) { return (int)((unsigned)q % TC); };
+  auto qv = [](int q) { return (int)((unsigned)q / TC); };
   // A published pivot p: masked column (A(i, p) on active rows i != p, else
   // 0), the update row z (A(c, p) on active columns, 1 at p, L^-1(p, c) on
   // eliminated columns), the diagonal A(p, p) and its reciprocal.
@@ -574,8 +578,8 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
   // publishes pivot q (block-uniform) into buffer s; the register slot is
   // picked by selects (no dynamic register indexing)
   auto publish = [&](int q, int s) {
-    if (tc == q % TC) {
-      const int w = q / TC;
+    if (tc == qc(q)) {
+      const int w = qv(q);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         double xr = mr[u][0], xi = mi[u][0];
@@ -624,8 +628,8 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
   };
   // column q of M := 0 (it is about to receive -l, the new column of L^-1)
   auto zero_col = [&](int q) {
-    if (tc == q % TC) {
-      const int w = q / TC;
+    if (tc == qc(q)) {
+      const int w = qv(q);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -637,7 +641,7 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
   };
   auto retire = [&](int q) {
     if (tr == (q & 15)) rowbits &= ~(1u << (q >> 4));
-    if (tc == q % TC) colbits &= ~(1u << (q / TC));
+    if (tc == qc(q)) colbits &= ~(1u << qv(q));
   };
 
   int pv = lane;   // physical row at position `lane`
