@@ -90,6 +90,7 @@ def run_path(case, vals, f, prec, steps, warmup, graph, tune, tiles=None, timed_
     kt = None
     if timed_events:
         kt = s.kernel_timer_read()
+        kt["factorizations"] = steps
         s.kernel_timer_start(None)
     info = s.info()
     sub = None
@@ -115,15 +116,16 @@ def kernel_timing(solver, vals, kernel="schur_update"):
     solver.factor(vals)
     torch.cuda.synchronize()
     kt = solver.kernel_timer_read()
+    kt["factorizations"] = 1
     solver.kernel_timer_start(None)
     return kt
 
 
-def recorded_traffic(workload, tiles):
+def recorded_traffic(workload, tiles, launches):
     """HBM bytes per Schur-update launch from the committed rocprofv3 counter
     record (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration), or
-    None when the kernels, the workload or the tile policy differ from the
-    measured ones."""
+    None when the kernels, the workload, the tile policy or the number of
+    launches per factorisation differ from the measured ones."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"schur_update_{workload}_traffic.json")
     if not os.path.exists(path):
@@ -133,6 +135,8 @@ def recorded_traffic(workload, tiles):
     with open(os.path.join(ROOT, "paper_2002_05019_amd", "csrc", "kernels.hip"), "rb") as fh:
         h = hashlib.sha256(fh.read()).hexdigest()
     if h != rec["kernels_hip_sha256"] or list(tiles or []) != rec["schur_tile_by_front_size"]:
+        return None
+    if launches != rec["launches"]:
         return None
     return rec["bytes_per_launch"]
 
@@ -294,7 +298,7 @@ def main():
             "kernel": "schur_update (complex FP32 MFMA trailing update, 64/128 tiles)", "bound": "mfma",
             "achieved": round(achieved, 3), "peak": PEAK["fp32_refine"], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK["fp32_refine"], 4),
-            "traffic": recorded_traffic(args.workload, mx["tiles"]),
+            "traffic": recorded_traffic(args.workload, mx["tiles"], kt["launches"] // kt["factorizations"]),
             "launches": kt["launches"], "avg_launch_us": round(kt["seconds"] / kt["launches"] * 1e6, 2)},
     }
     if "fp64" in res:

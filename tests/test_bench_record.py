@@ -1,0 +1,37 @@
+"""The committed Schur-update traffic record (no GPU): ``bench.py`` reports it
+only for the kernel source, tile policy and launch count it was measured on,
+and ``--gpus`` above 1 is refused."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _record():
+    with open(os.path.join(ROOT, "profiles", "schur_update_cube48_traffic.json")) as fh:
+        return json.load(fh)
+
+
+def test_record_matches_current_kernels():
+    rec = _record()
+    got = bench.recorded_traffic("cube48", rec["schur_tile_by_front_size"], rec["launches"])
+    assert got == rec["bytes_per_launch"] > 0
+
+
+def test_record_refused_for_other_plans():
+    rec = _record()
+    tiles = rec["schur_tile_by_front_size"]
+    assert bench.recorded_traffic("cube48", tiles, rec["launches"] + 1) is None
+    assert bench.recorded_traffic("cube48", [128] * len(tiles), rec["launches"]) is None
+    assert bench.recorded_traffic("no_such_workload", tiles, rec["launches"]) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr), r.stdout + r.stderr
