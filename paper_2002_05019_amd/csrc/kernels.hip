@@ -862,8 +862,13 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
 }
 
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
+// FP32: at most 128 registers (four waves per SIMD; 164 unbounded, no
+// spills at 128).  While the side stream's Schur update fills the CUs (five
+// 96-register workgroups per SIMD), a workgroup of this size fits as soon as
+// one of them retires; at 164 it needs two retirements on one CU and waits
+// until the update has no workgroups left to hand out.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_trsm(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64K32> sm;
   // W staging reuses the GEMM's LDS once the product is done (half the LDS
   // of the kernel, so its workgroups find room beside the side stream's)
