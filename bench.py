@@ -121,13 +121,13 @@ def kernel_timing(solver, vals, kernel="schur_update"):
     return kt
 
 
-def recorded_traffic(workload, tiles, launches):
+def recorded_traffic(workload, tiles, launches, path=None):
     """HBM bytes per Schur-update launch from the committed rocprofv3 counter
     record (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration), or
     None when the kernels, the workload, the tile policy or the number of
     launches per factorisation differ from the measured ones."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"schur_update_{workload}_traffic.json")
+    path = path or os.path.join(ROOT, "profiles", f"schur_update_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:

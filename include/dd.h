@@ -52,8 +52,12 @@ typedef enum {
     DD_ERR_MAP = -3,           /* malformed interface map                            */
     DD_ERR_STATE = -4,         /* call out of order (e.g. solve before factor)       */
     DD_ERR_NOMEM = -5,         /* workspace too small / host allocation failed       */
-    DD_ERR_SINGULAR = -6,      /* a pivot block had to be perturbed (see dd_info)    */
-    DD_ERR_NUMERIC = -7,       /* NaN/Inf met during factor or solve                 */
+    DD_ERR_SINGULAR = -6,      /* a pivot block had to be perturbed: the domain (or
+                                  auxiliary) matrix is singular to working
+                                  precision inside a pivot tile (dd_info says
+                                  where)                                          */
+    DD_ERR_NUMERIC = -7,       /* non-finite pivot in the factorisation, or a
+                                  non-finite refinement residual                  */
     DD_ERR_NOT_CONVERGED = -8, /* refinement hit refine_maxit above refine_tol      */
     DD_ERR_DEVICE = -9         /* a HIP runtime call failed                          */
 } dd_status;
@@ -97,8 +101,13 @@ typedef struct {
     int32_t precision;     /* DD_FP64, or DD_FP32_REFINE: complex FP32 fronts,
                               Schur updates and substitutions, FP64 pivot blocks,
                               FP64 residuals and refinement updates             */
-    double  refine_tol;    /* DD_FP32_REFINE: stop when every column has
-                              ||r|| / ||f|| <= refine_tol (default 1e-9)        */
+    double  refine_tol;    /* DD_FP32_REFINE: stop when every column has both
+                              residuals relative to its right-hand side at or
+                              below refine_tol (default 1e-9): the torn one,
+                              [f - K u - B^T lam; -B u], and the assembled one,
+                              f - A u~ with A = sum_i R_i^T K_i R_i and u~ every
+                              DoF's lowest-numbered copy (the residual of the
+                              undecomposed FEM system)                         */
     int32_t refine_maxit;  /* DD_FP32_REFINE: iteration cap (default 20)        */
     int32_t max_rhs;       /* columns per internal solve block; the workspace is
                               sized for it, larger nrhs are solved in blocks
@@ -136,15 +145,29 @@ typedef struct {
     int32_t max_front_aux;
     int32_t max_front_domain;
     int32_t refine_iters;   /* refinement iterations of the last dd_solve       */
-    double  rel_resid;      /* max over columns of ||r||/||f|| (refined solves) */
-    int32_t n_perturbed;    /* pivot blocks perturbed in the last dd_factor     */
-    int32_t numeric_flags;  /* nonzero if NaN/Inf was met                       */
+    double  rel_resid;      /* refined solves: max over columns of the assembled
+                               residual ||f - A u~|| / ||f|| (see refine_tol)   */
+    int32_t n_perturbed;    /* pivots perturbed in the last dd_factor           */
+    int32_t numeric_flags;  /* nonzero if a non-finite pivot was met            */
+    double  bytes_solve;    /* bytes of stored factors one solve of one column
+                               block reads (forward and backward sweeps)        */
+    double  rel_resid_torn; /* refined solves: max over columns of the torn
+                               residual ||[f - K u - B^T lam; -B u]|| / ||f||   */
+    int32_t bad_domain;     /* lowest domain with a perturbed or non-finite
+                               pivot, n_dom for the auxiliary matrix, -1 none   */
+    int32_t n_pivot_2x2;    /* 2 x 2 pivots chosen by the last dd_factor        */
+    int32_t n_interchanges; /* pivot interchanges inside the pivot tiles         */
+    int32_t reserved_;
 } dd_info;
 
 /* Defaults listed above. */
 void dd_default_options(dd_options *opt);
 
-/* Symbolic phase, host only (no GPU call): validates the problem, orders every
+/* Symbolic phase, host only (no GPU call).  Section II: the decomposed
+ * problem has primal DoFs in the domains and dual DoFs on the interfaces; the
+ * domains are eliminated by independent sparse direct factorisations, and the
+ * auxiliary matrix is factored after a symbolic step on the clique graph of
+ * its block-wise sparse structure.  Here: validates the problem, orders every
  * domain by nested dissection with its interface DoFs last, builds the
  * multifrontal trees, groups the multipliers into blocks with identical domain
  * pairs, orders the block (clique) graph of the auxiliary matrix, and plans the
@@ -161,16 +184,29 @@ dd_status dd_workspace_size(dd_ctx ctx, int64_t *bytes);
  * the next bind.  Errors: DD_ERR_NOMEM (too small), DD_ERR_DEVICE. */
 dd_status dd_bind_workspace(dd_ctx ctx, void *dev_ptr, int64_t bytes);
 
-/* Numeric factorisation, enqueued on hip_stream (a hipStream_t; NULL = the
+/* Numeric factorisation (section II: the primal DoFs of every domain are
+ * eliminated by independent sparse LDL^T factorisations, leaving the dual
+ * blocks B_i K_i^-1 B_i^T; their sum, the symmetric block-wise sparse
+ * auxiliary matrix, is factored by a block LDL^T with restricted
+ * Bunch-Kaufman pivoting), enqueued on hip_stream (a hipStream_t; NULL = the
  * null stream).  vals: device array of the values of all domain matrices
  * concatenated in domain order, nnz_i each in the CSR order of dd_setup's
  * patterns.  The values are read during the call's stream work only (FP32
  * mode keeps an FP64 copy in the workspace for refinement).
- * Returns after enqueueing; numerical problems (perturbed pivots, NaN) are
- * reported by dd_get_info and by the status of the next dd_solve. */
+ * Returns after enqueueing.  Numerical problems are reported by dd_get_info
+ * and by the next dd_solve / dd_solve_subset, which waits for the
+ * factorisation to finish and reads its status words: a non-finite pivot
+ * gives DD_ERR_NUMERIC (nothing is solved); perturbed pivots give
+ * DD_ERR_SINGULAR in FP64 mode (the solution of the perturbed factors is
+ * still written) and in FP32_REFINE mode only when the refinement does not
+ * reach refine_tol. */
 dd_status dd_factor(dd_ctx ctx, const dd_z *vals, void *hip_stream);
 
-/* Solves the arrowhead system for nrhs right-hand sides.
+/* Solves the arrowhead system for nrhs right-hand sides (section II: the
+ * condensed right-hand side gives the multipliers through the factored
+ * auxiliary matrix, then the primal unknowns of every domain are recovered by
+ * independent forward/backward substitutions; section III: many
+ * excitations).
  * f: device, torn right-hand sides, column-major with leading dimension ldf
  *    >= sum n_i; rows of domain i start at sum_{j<i} n_j.
  * u: device output in the same layout (ldu >= sum n_i); may not alias f.
@@ -178,7 +214,9 @@ dd_status dd_factor(dd_ctx ctx, const dd_z *vals, void *hip_stream);
  *    with leading dimension ldl >= n_mult (NULL to skip).
  * FP32 mode refines in FP64 until refine_tol (DD_ERR_NOT_CONVERGED if the cap
  * is hit; u and lam still hold the last iterate).  FP64 mode is asynchronous
- * on hip_stream; FP32 mode synchronises the stream once per refinement step. */
+ * on hip_stream apart from the status check: the first solve after a
+ * dd_factor waits for the factorisation to finish (see dd_factor for the
+ * codes).  FP32 mode synchronises the stream once per refinement step. */
 dd_status dd_solve(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u,
                    int64_t ldu, dd_z *lam, int64_t ldl, void *hip_stream);
 
@@ -230,8 +268,10 @@ enum {
 dd_status dd_kernel_timer_start(dd_ctx ctx, int32_t kernel);
 dd_status dd_kernel_timer_read(dd_ctx ctx, double *seconds, int64_t *launches, double *flops);
 
-/* Tile autotuner (batching of uneven fronts, section II's many small dense
- * operations): for every front-size bucket that has fronts, times the first
+/* Tile autotuner for the batched factorisation of uneven fronts (section II
+ * builds the method on many independent dense operations, to expose
+ * concurrency for parallel and GPU processing): for every front-size bucket
+ * that has fronts, times the first
  * outer block's Schur update of all its fronts with 64 x 64 and 128 x 128
  * tiles on the bound workspace (a few launches each, events on hip_stream),
  * keeps the faster one, re-plans the launch sequences with that policy and

@@ -162,6 +162,20 @@ def global_residual(case, u_torn):
     return np.linalg.norm(r, axis=0) / np.linalg.norm(case.f, axis=0)
 
 
+def cond1_estimate(A):
+    """Estimate of the 1-norm condition number ||A||_1 ||A^-1||_1, the inverse's
+    norm by Hager-Higham block estimation (scipy onenormest) on SuperLU
+    solves.  It bounds the relative error of a solution by its relative
+    residual: err <= cond * resid."""
+    lu = spl.splu(sp.csc_matrix(A))
+    n = A.shape[0]
+    inv = spl.LinearOperator((n, n), matvec=lambda x: lu.solve(np.asarray(x, complex)),
+                             rmatvec=lambda x: lu.solve(np.asarray(x, complex), trans="H"),
+                             matmat=lambda X: lu.solve(np.asarray(X, complex)), dtype=complex)
+    anorm = np.abs(sp.csc_matrix(A)).sum(axis=0).max()
+    return float(anorm * spl.onenormest(inv))
+
+
 def rel_error(u, ref):
     """Per-column ||u - ref||_2 / ||ref||_2."""
     u = np.asarray(u).reshape(ref.shape[0], -1)

@@ -45,7 +45,9 @@ class dd_info(C.Structure):
                 ("flops_factor", C.c_double), ("flops_solve", C.c_double), ("bytes_factor", C.c_double),
                 ("workspace_bytes", C.c_int64), ("n_fronts_domain", C.c_int32), ("n_fronts_aux", C.c_int32),
                 ("max_front_aux", C.c_int32), ("max_front_domain", C.c_int32), ("refine_iters", C.c_int32),
-                ("rel_resid", C.c_double), ("n_perturbed", C.c_int32), ("numeric_flags", C.c_int32)]
+                ("rel_resid", C.c_double), ("n_perturbed", C.c_int32), ("numeric_flags", C.c_int32),
+                ("bytes_solve", C.c_double), ("rel_resid_torn", C.c_double), ("bad_domain", C.c_int32),
+                ("n_pivot_2x2", C.c_int32), ("n_interchanges", C.c_int32), ("reserved_", C.c_int32)]
 
 
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
@@ -173,11 +175,13 @@ class Solver:
         self._ws = None
 
     @classmethod
-    def from_case(cls, case, **kw):
+    def from_case(cls, case, coordinates=True, **kw):
+        """Solver of a generated case; ``coordinates=False`` passes no DoF
+        coordinates (graph-only orderings)."""
         doms = case.domains
+        xyz = np.concatenate([d.xyz for d in doms]) if coordinates else None
         return cls([d.K.indptr for d in doms], [d.K.indices for d in doms], case.n_mult, case.imap_ptr,
-                   case.imap_dof, case.imap_mult, case.imap_sign,
-                   xyz=np.concatenate([d.xyz for d in doms]), **kw)
+                   case.imap_dof, case.imap_mult, case.imap_sign, xyz=xyz, **kw)
 
     # ------------------------------------------------------------------ device
     @staticmethod
@@ -204,9 +208,12 @@ class Solver:
         self._vals = vals
         _check(self._lib.dd_factor(self._ctx, C.c_void_p(vals.data_ptr()), self._stream(stream)))
 
-    def solve(self, f, return_lam=False, stream=None):
+    def solve(self, f, return_lam=False, stream=None, check=True):
         """f: complex128 device tensor (n_torn, nrhs) (or (n_torn,)).  Returns u
-        of the same shape (and the multipliers (n_mult, nrhs) if asked)."""
+        of the same shape (and the multipliers (n_mult, nrhs) if asked).
+        A status other than DD_OK raises DDError unless ``check`` is False;
+        the status is kept in ``last_status`` either way (u is written on
+        DD_ERR_NOT_CONVERGED and DD_ERR_SINGULAR)."""
         import torch
         vec = f.dim() == 1
         F = f.reshape(self.n_torn, -1)
@@ -218,7 +225,7 @@ class Solver:
                                 self.n_torn, C.c_void_p(lam.data_ptr()) if lam is not None else None,
                                 max(self.n_mult, 1), self._stream(stream))
         self.last_status = st
-        if st not in (DD_OK, -8):
+        if check:
             _check(st)
         u = u.t()
         if vec:
@@ -227,7 +234,7 @@ class Solver:
             return u, lam.t()
         return u
 
-    def solve_subset(self, f, domains, u=None, stream=None):
+    def solve_subset(self, f, domains, u=None, stream=None, check=True):
         """Recovers the primal unknowns of the listed domains only (FP64
         contexts).  f: complex128 device tensor (n_torn, nrhs); u: optional
         output of the same shape whose other rows are left as they are
@@ -243,7 +250,8 @@ class Solver:
                                        C.c_void_p(uc.data_ptr()), self.n_torn, _ptr(mask, C.c_uint8),
                                        self._stream(stream))
         self.last_status = st
-        _check(st)
+        if check:
+            _check(st)
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         out = uc.t()
         return out.reshape(-1) if f.dim() == 1 else out

@@ -48,7 +48,11 @@ struct dd_ctx_s {
   hipStream_t last = nullptr;
   double t_setup = 0;
   int refine_iters = 0;
-  double rel_resid = 0;
+  double rel_resid = 0, rel_resid_torn = 0;
+  // status words of the last factorisation (see read_status); valid once
+  // status_read is set
+  bool status_read = false;
+  int32_t stat[5] = {0, 0, 0, 0, 0};
   dd::KTimer tm;
   std::vector<hipEvent_t> tev;
   // hipGraph replay: captured on an internal stream, launched on the caller's
@@ -83,6 +87,40 @@ hipError_t capture(dd_ctx_s *c, F enqueue, hipGraphExec_t *out) {
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   return e;
+}
+
+// Waits for the last factorisation to finish and reads its status words
+// (perturbed pivots, non-finite flag, 2 x 2 pivots, interchanges, lowest
+// domain with a perturbed or non-finite pivot) through the internal stream.
+hipError_t read_status(dd_ctx_s *c) {
+  if (c->status_read) return hipSuccess;
+  hipError_t e = hipEventSynchronize(c->ev[1]);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->stat, c->ws + c->plan.b_status, sizeof c->stat, hipMemcpyDeviceToHost, c->cap);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->cap);
+  if (e == hipSuccess) c->status_read = true;
+  return e;
+}
+
+std::string where_msg(const dd_ctx_s *c) {
+  const int d = c->stat[4];
+  if (d >= c->plan.n_dom) return "the auxiliary matrix";
+  return "domain " + std::to_string(d);
+}
+
+// Status that the solve reports for the factorisation: DD_ERR_NUMERIC for a
+// non-finite pivot (nothing is solved), DD_ERR_SINGULAR for perturbed
+// pivots (the solve still runs on the perturbed factors), else DD_OK.
+dd_status factor_status(const dd_ctx_s *c) {
+  if (c->stat[1]) {
+    g_err = "non-finite pivot in " + where_msg(c);
+    return DD_ERR_NUMERIC;
+  }
+  if (c->stat[0]) {
+    g_err = std::to_string(c->stat[0]) + " pivot block(s) perturbed, the first in " + where_msg(c);
+    return DD_ERR_SINGULAR;
+  }
+  return DD_OK;
 }
 
 hipError_t run_solve_core(dd_ctx_s *c, int nrhs, bool with_c, hipStream_t st, bool subset = false) {
@@ -268,6 +306,7 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
   HIPCHECK(hipEventRecord(c->ev[1], st));
   c->fact_rec = true;
   c->factored = true;
+  c->status_read = false;
   c->last = st;
   return DD_OK;
 }
@@ -284,11 +323,15 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
   if (lam && ldl < P.n_mult) return fail(DD_ERR_ARG, "ldl below n_mult");
   if ((const void *)f == (const void *)u) return fail(DD_ERR_ARG, "u may not alias f");
   hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(read_status(c));
+  const dd_status fst = factor_status(c);
+  if (fst == DD_ERR_NUMERIC) return fst;
   c->last = st;
   HIPCHECK(hipEventRecord(c->ev[2], st));
   dd_status result = DD_OK;
   c->refine_iters = 0;
   c->rel_resid = 0;
+  c->rel_resid_torn = 0;
   for (int32_t j0 = 0; j0 < nrhs; j0 += P.max_rhs) {
     const int nb = std::min<int32_t>(P.max_rhs, nrhs - j0);
     const dd_z *fj = f + (int64_t)j0 * ldf;
@@ -300,34 +343,45 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
       HIPCHECK(dd::sol_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
       continue;
     }
-    // FP64 iterative refinement with the FP32 factors
-    std::vector<double> fn(nb), rn(nb);
+    // FP64 iterative refinement with the FP32 factors.  Two residuals per
+    // column, both relative to the right-hand side: the torn one,
+    // [f - K u - B^T lam; -B u], whose FP32 solve gives the correction, and
+    // the assembled one, f - A u~ with every DoF taken from its
+    // representative copy (the residual of the undecomposed FEM system,
+    // A = sum_i R_i^T K_i R_i).  Stop when both are within refine_tol.
+    const int64_t mr = P.max_rhs;
+    std::vector<double> fn(2 * nb), rn(2 * nb);
     double *r64 = (double *)(c->ws + P.b_r64);
     HIPCHECK(dd::refine_init(P, c->ws, nb, st));
     HIPCHECK(dd::refine_resid(P, c->ws, fj, ldf, nb, true, st));
     HIPCHECK(hipMemcpyAsync(fn.data(), r64 + P.r_fnorm, nb * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(fn.data() + nb, r64 + P.r_fnorm + mr, nb * 8, hipMemcpyDeviceToHost, st));
     int it = 0;
-    double rel = 0;
+    double rel_t = 0, rel_g = 0;
     for (;;) {
       HIPCHECK(dd::refine_resid(P, c->ws, fj, ldf, nb, false, st));
       HIPCHECK(hipMemcpyAsync(rn.data(), r64 + P.r_norm, nb * 8, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(rn.data() + nb, r64 + P.r_norm + mr, nb * 8, hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
-      rel = 0;
+      rel_t = rel_g = 0;
       bool bad = false;
       for (int j = 0; j < nb; ++j) {
-        double r = fn[j] > 0 ? std::sqrt(rn[j] / fn[j]) : std::sqrt(rn[j]);
-        if (!std::isfinite(r)) bad = true;
-        rel = std::max(rel, r);
+        const double rt = fn[j] > 0 ? std::sqrt(rn[j] / fn[j]) : std::sqrt(rn[j]);
+        const double rg = fn[nb + j] > 0 ? std::sqrt(rn[nb + j] / fn[nb + j]) : std::sqrt(rn[nb + j]);
+        if (!std::isfinite(rt) || !std::isfinite(rg)) bad = true;
+        rel_t = std::max(rel_t, rt);
+        rel_g = std::max(rel_g, rg);
       }
       if (bad) {
         result = DD_ERR_NUMERIC;
         g_err = "non-finite residual during refinement";
         break;
       }
-      if (rel <= c->opt.refine_tol) break;
+      if (std::max(rel_t, rel_g) <= c->opt.refine_tol) break;
       if (it >= c->opt.refine_maxit) {
-        result = DD_ERR_NOT_CONVERGED;
-        g_err = "refinement did not reach refine_tol";
+        // perturbed pivots are the likely cause: report them
+        result = fst != DD_OK ? fst : DD_ERR_NOT_CONVERGED;
+        if (fst == DD_OK) g_err = "refinement did not reach refine_tol";
         break;
       }
       HIPCHECK(run_solve_core(c, nb, true, st));
@@ -336,10 +390,17 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
     }
     HIPCHECK(dd::refine_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
     c->refine_iters = std::max(c->refine_iters, it);
-    c->rel_resid = std::max(c->rel_resid, rel);
+    c->rel_resid = std::max(c->rel_resid, rel_g);
+    c->rel_resid_torn = std::max(c->rel_resid_torn, rel_t);
   }
   HIPCHECK(hipEventRecord(c->ev[3], st));
   c->solve_rec = true;
+  // FP64: perturbed pivots make the solution inexact (no refinement repairs
+  // it); FP32_REFINE: a refinement that reached refine_tol repaired them
+  if (result == DD_OK && P.precision == 0 && fst != DD_OK) {
+    factor_status(c);
+    result = fst;
+  }
   return result;
 }
 
@@ -358,6 +419,9 @@ dd_status dd_solve_subset(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd
   if ((const void *)f == (const void *)u) return fail(DD_ERR_ARG, "u may not alias f");
   try {
     hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(read_status(c));
+    const dd_status fst = factor_status(c);
+    if (fst == DD_ERR_NUMERIC) return fst;
     c->last = st;
     HIPCHECK(hipMemcpyAsync(c->ws + P.b_dmask, domain_mask, (size_t)P.n_dom, hipMemcpyHostToDevice, st));
     HIPCHECK(hipEventRecord(c->ev[2], st));
@@ -371,6 +435,10 @@ dd_status dd_solve_subset(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd
     }
     HIPCHECK(hipEventRecord(c->ev[3], st));
     c->solve_rec = true;
+    if (fst != DD_OK) {
+      factor_status(c);
+      return fst;
+    }
   } catch (...) {
     return fail(DD_ERR_DEVICE, "unexpected exception");
   }
@@ -385,6 +453,7 @@ dd_status dd_get_info(dd_ctx c, dd_info *info) {
   info->flops_factor = P.flops_factor;
   info->flops_solve = P.flops_solve_rhs;
   info->bytes_factor = P.bytes_factor;
+  info->bytes_solve = P.bytes_solve;
   info->workspace_bytes = P.b_total;
   info->n_fronts_domain = P.n_front_dom;
   info->n_fronts_aux = P.n_front_aux;
@@ -392,6 +461,8 @@ dd_status dd_get_info(dd_ctx c, dd_info *info) {
   info->max_front_domain = P.max_front_dom;
   info->refine_iters = c->refine_iters;
   info->rel_resid = c->rel_resid;
+  info->rel_resid_torn = c->rel_resid_torn;
+  info->bad_domain = -1;
   if (c->events) {
     float ms = 0;
     if (c->fact_rec) {
@@ -406,11 +477,13 @@ dd_status dd_get_info(dd_ctx c, dd_info *info) {
     }
   }
   if (c->ws && c->factored) {
-    int st[2] = {0, 0};
     HIPCHECK(hipStreamSynchronize(c->last));
-    HIPCHECK(hipMemcpy(st, c->ws + P.b_status, sizeof st, hipMemcpyDeviceToHost));
-    info->n_perturbed = st[0];
-    info->numeric_flags = st[1];
+    HIPCHECK(read_status(c));
+    info->n_perturbed = c->stat[0];
+    info->numeric_flags = c->stat[1];
+    info->n_pivot_2x2 = c->stat[2];
+    info->n_interchanges = c->stat[3];
+    if (c->stat[0] || c->stat[1]) info->bad_domain = c->stat[4];
   }
   return DD_OK;
 }

@@ -52,6 +52,13 @@ struct KP {
   // substitution (null: every domain)
   const uint8_t *dmask;
   const Item *gemv;
+  // copies of each global DoF (FP64 refinement): representative torn row,
+  // component pointers and rows
+  const int32_t *grep;
+  const int32_t *gcp;
+  const int32_t *gcr;
+  int64_t n_gcomp;
+  int64_t rg;      // offset (doubles) of the assembled-residual rows in r64
   T *num;
   cd *dinv;
   cd *doff;
@@ -645,7 +652,7 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
   };
 
   int pv = lane;   // physical row at position `lane`
-  int npert = 0;
+  int npert = 0, n2 = 0, nswap = 0;   // perturbed pivots, 2 x 2 pivots, interchanges
   int j = 0, cur = 0;
   publish(0, 0);
   __syncthreads();
@@ -705,6 +712,8 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
       kind = __builtin_amdgcn_readfirstlane(kind);
       piv = __builtin_amdgcn_readfirstlane(piv);
       const int q = kind == 1 ? j : j + 1;
+      nswap += piv != q;
+      n2 += kind == 2;
       if (piv != q) {
         // interchange of positions q and piv: only the order changes
         const int a0 = __builtin_amdgcn_readlane(pv, q), a1 = __builtin_amdgcn_readlane(pv, piv);
@@ -857,8 +866,22 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
     p.perm[s] = pv;
     if (!isfinite(dvr[tid]) || !isfinite(dvi[tid])) bad = true;
   }
-  if (bad) atomicOr(p.status + 1, 1);
-  if (tid == 0 && npert) atomicAdd(p.status, npert);
+  // status words: [0] perturbed pivots, [1] non-finite flag, [2] 2 x 2
+  // pivots, [3] interchanges, [4] lowest domain with a perturbed or
+  // non-finite pivot (n_dom: the auxiliary matrix)
+  const int where = f.dom >= 0 ? f.dom : p.n_dom;
+  if (bad) {
+    atomicOr(p.status + 1, 1);
+    atomicMin(p.status + 4, where);
+  }
+  if (tid == 0) {
+    if (npert) {
+      atomicAdd(p.status, npert);
+      atomicMin(p.status + 4, where);
+    }
+    if (n2) atomicAdd(p.status + 2, n2);
+    if (nswap) atomicAdd(p.status + 3, nswap);
+  }
 }
 
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
@@ -2374,11 +2397,15 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
 #pragma unroll
       for (int q = 0; q < 8; ++q) rr[q] = ri[q] = 0;
       if (e < nt) {
+        // gr, gi: the same row of f - K u~, u~ taking every DoF's value from
+        // its representative copy; summed over the copies of a DoF this is
+        // the residual of the assembled (undecomposed) system
+        double gr[8], gi[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const cd fv = f[e + jc[q] * ldf];
-          rr[q] = fv.re;
-          ri[q] = fv.im;
+          rr[q] = gr[q] = fv.re;
+          ri[q] = gi[q] = fv.im;
         }
         if (!fnorm) {
           // SELL-64: the wave's 64 rows form one slice, entry k of all its
@@ -2388,16 +2415,21 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
           for (int64_t z = zb + (e & 63); z < zw; z += 64) {
             const cd a = p.vals[z];
             const int64_t c = p.sellc[z];
-            double ur[8], ui[8];
+            const int64_t cg = p.grep[c];
+            double ur[8], ui[8], vr[8], vi[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               ur[q] = U[c + jc[q] * nt];
               ui[q] = U[c + jc[q] * nt + nt * mr];
+              vr[q] = U[cg + jc[q] * nt];
+              vi[q] = U[cg + jc[q] * nt + nt * mr];
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               rr[q] -= a.re * ur[q] - a.im * ui[q];
               ri[q] -= a.re * ui[q] + a.im * ur[q];
+              gr[q] -= a.re * vr[q] - a.im * vi[q];
+              gi[q] -= a.re * vi[q] + a.im * vr[q];
             }
           }
           const int gidx = p.rowgam[e];
@@ -2421,6 +2453,13 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
               vf[e + (j0 + q) * nt + nt * mr] = (T)ri[q];
             }
         }
+        double *G = p.r64 + p.rg;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nj) {
+            G[e + (j0 + q) * nt] = gr[q];
+            G[e + (j0 + q) * nt + nt * mr] = gi[q];
+          }
       } else if (!fnorm) {
         const int64_t m = e - nt;
         const MultRef R = p.mrefs[m];
@@ -2441,6 +2480,51 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] += rr[q] * rr[q] + ri[q] * ri[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x < nj) part[blockIdx.x + (int64_t)(j0 + threadIdx.x) * gridDim.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// Assembled residual: per global DoF (component of copies) the sum of its
+// rows of f - K u~, squared and summed per column into per-block partials.
+template <typename T>
+__global__ __launch_bounds__(256) void k_r_gsum(KP<T> p, int nrhs, int64_t part_off) {
+  __shared__ double red[8][256];
+  const int64_t mr = p.mr, nt = p.n_torn;
+  const double *G = p.r64 + p.rg;
+  double *part = p.r64 + part_off;
+  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+    const int nj = min(8, nrhs - j0);
+    int64_t jc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) jc[q] = min(j0 + q, nrhs - 1);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < p.n_gcomp; c += (int64_t)gridDim.x * 256) {
+      double sr[8], si[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sr[q] = si[q] = 0;
+      for (int k = p.gcp[c]; k < p.gcp[c + 1]; ++k) {
+        const int64_t r = p.gcr[k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          sr[q] += G[r + jc[q] * nt];
+          si[q] += G[r + jc[q] * nt + nt * mr];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += sr[q] * sr[q] + si[q] * si[q];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = acc[q];
@@ -2514,6 +2598,11 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
   k.domrow = (const int64_t *)(m + P.m_domrow);
   k.dmask = nullptr;
   k.gemv = (const Item *)(m + P.m_gemv);
+  k.grep = (const int32_t *)(m + P.m_grep);
+  k.gcp = (const int32_t *)(m + P.m_gcp);
+  k.gcr = (const int32_t *)(m + P.m_gcr);
+  k.n_gcomp = P.n_gcomp;
+  k.rg = P.r_g;
   k.num = (T *)(ws + P.b_num);
   uint8_t *sd = ws + P.b_side;
   k.dinv = (cd *)sd;
@@ -2613,7 +2702,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
 
 // clears the status words (a kernel, so that graph capture records no memset)
 __global__ void k_zero_status(int *status) {
-  if (threadIdx.x < 2) status[threadIdx.x] = 0;
+  if (threadIdx.x < 5) status[threadIdx.x] = threadIdx.x == 4 ? 0x7fffffff : 0;
 }
 
 template <typename T>
@@ -2728,8 +2817,11 @@ hipError_t refine_resid(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, 
   hipLaunchKernelGGL(k_r_resid<float>, dim3(nb), dim3(256), 0, st, k, (const cd *)f, ldf, nrhs, P.r_part,
                      fnorm ? 1 : 0);
   double *r64 = (double *)(ws + P.b_r64);
-  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + P.r_part, nb, nrhs,
-                     r64 + (fnorm ? P.r_fnorm : P.r_norm));
+  double *out = r64 + (fnorm ? P.r_fnorm : P.r_norm);
+  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + P.r_part, nb, nrhs, out);
+  const int64_t gpart = P.r_part + P.r_nblk * P.max_rhs;
+  hipLaunchKernelGGL(k_r_gsum<float>, dim3(nb), dim3(256), 0, st, k, nrhs, gpart);
+  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + gpart, nb, nrhs, out + P.max_rhs);
   return hipGetLastError();
 }
 hipError_t refine_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,

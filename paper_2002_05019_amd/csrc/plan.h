@@ -106,6 +106,13 @@ struct Plan {
   std::vector<GamRef> grefs;
   std::vector<int32_t> hmult, hsign;
   std::vector<int32_t> row_gam;
+  // copies of one global DoF: the torn rows that multipliers tie together
+  // (union of the multiplier pairs).  grep[r] = lowest torn row of r's
+  // component (its representative); the components in representative order,
+  // gcomp_row[gcomp_ptr[c] .. gcomp_ptr[c+1]) their rows (FP64 refinement:
+  // residual of the assembled system)
+  std::vector<int32_t> grep, gcomp_ptr, gcomp_row;
+  int64_t n_gcomp = 0;
 
   // ---- schedule
   std::vector<Item> items;
@@ -132,14 +139,16 @@ struct Plan {
   int64_t b_meta = 0, b_num = 0, b_side = 0, b_vals = 0, b_r64 = 0, b_status = 0, b_dmask = 0, b_total = 0;
   // offsets (bytes) of each meta array inside the meta blob
   int64_t m_fronts, m_vars, m_cfront, m_crmap, m_rmap, m_spairs, m_aux, m_gpos, m_gsign,
-      m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_sellp, m_sellc, m_domrow;
+      m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_sellp, m_sellc, m_domrow,
+      m_grep, m_gcp, m_gcr;
   std::vector<uint8_t> meta;           // serialised meta blob
   // FP64 refinement vectors (doubles, planar) inside the r64 region
-  int64_t r_u = 0, r_l = 0, r_ru = 0, r_rl = 0, r_norm = 0, r_fnorm = 0, r_part = 0;
+  // r_g: per torn row f - K u~ with u~ the representative copies (FP64 planar)
+  int64_t r_u = 0, r_l = 0, r_g = 0, r_norm = 0, r_fnorm = 0, r_part = 0;
   int64_t r_nblk = 0;
 
   // ---- statistics
-  double flops_factor = 0, flops_solve_rhs = 0, bytes_factor = 0;
+  double flops_factor = 0, flops_solve_rhs = 0, bytes_factor = 0, bytes_solve = 0;
   int32_t n_front_dom = 0, n_front_aux = 0, max_front_dom = 0, max_front_aux = 0;
 };
 

@@ -813,6 +813,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.flops_factor = fl;
   P.flops_solve_rhs = fs;
   P.bytes_factor = fb;
+  // one solve of one column block reads every stored factor twice (forward
+  // and backward sweeps; the interface inverses in the condensation and in
+  // the interface correction)
+  P.bytes_solve = 2.0 * fb;
 
   // ------------------------------------------------------------ numeric layout (T elements)
   const int64_t mr = P.max_rhs;
@@ -876,6 +880,41 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       r.row[s] = P.dom_row[d] + m_dof[2 * m + s];
     }
     P.mrefs[m] = r;
+  }
+  // copies of every global DoF (FP64 refinement): union-find over the torn
+  // rows that a multiplier ties together; the representative of a component
+  // is its lowest torn row (the copy of the lowest-numbered domain)
+  if (o.precision != 0) {
+    std::vector<int32_t> up(P.n_torn);
+    std::iota(up.begin(), up.end(), 0);
+    auto find = [&](int32_t x) {
+      while (up[x] != x) {
+        up[x] = up[up[x]];
+        x = up[x];
+      }
+      return x;
+    };
+    for (int64_t m = 0; m < p.n_mult; ++m) {
+      int32_t a = find((int32_t)P.mrefs[m].row[0]), b = find((int32_t)P.mrefs[m].row[1]);
+      if (a != b) up[std::max(a, b)] = std::min(a, b);
+    }
+    P.grep.resize(P.n_torn);
+    std::vector<int32_t> cid(P.n_torn, -1), cnt;
+    for (int64_t r = 0; r < P.n_torn; ++r) {
+      const int32_t g = find((int32_t)r);
+      P.grep[r] = g;
+      if (g == r) {
+        cid[r] = (int32_t)cnt.size();
+        cnt.push_back(0);
+      }
+      cnt[cid[g]]++;
+    }
+    P.n_gcomp = (int64_t)cnt.size();
+    P.gcomp_ptr.assign(P.n_gcomp + 1, 0);
+    for (int64_t c = 0; c < P.n_gcomp; ++c) P.gcomp_ptr[c + 1] = P.gcomp_ptr[c] + cnt[c];
+    P.gcomp_row.resize(P.n_torn);
+    std::vector<int32_t> fill(P.gcomp_ptr.begin(), P.gcomp_ptr.end() - 1);
+    for (int64_t r = 0; r < P.n_torn; ++r) P.gcomp_row[fill[cid[P.grep[r]]]++] = (int32_t)r;
   }
   // interface positions -> multipliers acting on them
   P.row_gam.assign(P.n_torn, -1);
@@ -1305,6 +1344,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.m_sellp = put(P.sell_ptr.data(), P.sell_ptr.size() * 8);
   P.m_sellc = put(P.sell_col.data(), P.sell_col.size() * 4);
   P.m_domrow = put(P.dom_row.data(), P.dom_row.size() * 8);
+  P.m_grep = put(P.grep.data(), P.grep.size() * 4);
+  P.m_gcp = put(P.gcomp_ptr.data(), P.gcomp_ptr.size() * 4);
+  P.m_gcr = put(P.gcomp_row.data(), P.gcomp_row.size() * 4);
 
   // ------------------------------------------------------------ workspace (bytes)
   auto A256 = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
@@ -1319,12 +1361,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     int64_t r = 0;
     P.r_u = r; r += 2 * P.n_torn * mr;
     P.r_l = r; r += 2 * P.n_mult * mr;
-    P.r_ru = r; r += 2 * P.n_torn * mr;
-    P.r_rl = r; r += 2 * P.n_mult * mr;
+    P.r_g = r; r += 2 * P.n_torn * mr;
     P.r_nblk = 1024;
-    P.r_part = r; r += 2 * P.r_nblk * mr;   // [blocks x cols] residual / rhs partial sums
-    P.r_norm = r; r += 2 * mr;
-    P.r_fnorm = r; r += mr;
+    // [blocks x cols] partial sums: torn residual (or rhs), then the
+    // assembled (global) one
+    P.r_part = r; r += 2 * P.r_nblk * mr;
+    P.r_norm = r; r += 2 * mr;    // squared norms: torn [0, mr), global [mr, 2 mr)
+    P.r_fnorm = r; r += 2 * mr;
     b = A256(b + r * 8);
   }
   P.b_status = b; b = A256(b + 256);

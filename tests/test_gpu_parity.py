@@ -1,9 +1,10 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
 Tolerances: FP64 path, relative error <= 1e-10 per right-hand-side column on
-the solution (and on the interface inverses); FP32 fronts + FP64 refinement,
-relative residual <= 1e-9 and the error against the FP64 oracle is reported
-and bounded.
+the solution, the multipliers and the interface inverses; FP32 fronts + FP64
+refinement, the residual of the undecomposed system ||f - A u|| / ||f|| <= 1e-9
+per column (computed on the host from the owner copies) and the error against
+the FP64 oracle <= 1e-9 per column.
 """
 import numpy as np
 import pytest
@@ -69,8 +70,9 @@ def test_solution_fp64(name):
     ref = _ref(name)
     eu = _colerr(u.cpu().numpy(), ref["u"])
     el = _colerr(lam.cpu().numpy(), ref["lam"])
+    print(f"[parity] {name} fp64: u err {eu:.2e} lam err {el:.2e}", flush=True)
     assert eu < 1e-10, eu
-    assert el < 1e-9, el
+    assert el < 1e-10, el
     assert oracle.global_residual(c, u.cpu().numpy()).max() < 1e-10
 
 
@@ -86,11 +88,13 @@ def test_solution_mixed_refined(name):
     gr = oracle.global_residual(c, un).max()
     eu = _colerr(un, _ref(name)["u"])
     print(f"[parity] {name} mixed: iters {info['refine_iters']} resid {info['rel_resid']:.2e} "
-          f"global resid {gr:.2e} err {eu:.2e}", flush=True)
+          f"(torn {info['rel_resid_torn']:.2e}) host global resid {gr:.2e} err {eu:.2e}", flush=True)
     assert s.last_status == 0
-    assert info["rel_resid"] <= 1e-9
-    assert gr < 1e-8
-    assert eu < 1e-7
+    assert info["rel_resid"] <= 1e-9 and info["rel_resid_torn"] <= 1e-9
+    # the device's assembled residual is the host's, up to rounding
+    assert abs(info["rel_resid"] - gr) <= 1e-3 * gr + 1e-15
+    assert gr <= 1e-9
+    assert eu <= 1e-9
 
 
 def test_many_rhs_blocks_and_vector_rhs():
@@ -172,8 +176,10 @@ def test_tuned_tiles(precision):
     s.factor(vals)
     u = s.solve(_rhs(c))
     torch.cuda.synchronize()
-    tol = 1e-10 if precision == "fp64" else 1e-7
+    tol = 1e-10 if precision == "fp64" else 1e-9
     assert _colerr(u.cpu().numpy(), _ref("cube24")["u"]) < tol
+    if precision == "fp32_refine":
+        assert oracle.global_residual(c, u.cpu().numpy()).max() <= 1e-9
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
@@ -191,7 +197,7 @@ def test_many_rhs_on_matrix_cores(precision):
     s = _solver(c, precision=precision, max_rhs=80)
     u = s.solve(torch.from_numpy(ft).to(DEV))
     torch.cuda.synchronize()
-    tol = 1e-10 if precision == "fp64" else 1e-7
+    tol = 1e-10 if precision == "fp64" else 1e-9
     assert _colerr(u.cpu().numpy(), ref["u"]) < tol
     if precision == "fp32_refine":
         assert s.info()["rel_resid"] <= 1e-9

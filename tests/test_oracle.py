@@ -185,3 +185,55 @@ def test_planted_mistakes_are_caught(c6, monkeypatch):
         assert oracle.rel_error(c_bad.owner_copy(bad["u"]), u_ref).max() > 1e-6
     finally:
         c_bad.imap_sign[:] = sign
+
+
+def test_residuals_grow_on_wrong_solutions(c6, dd6):
+    """The residual checks that gate the full-size runs are pinned to closed
+    forms on wrong solutions: since A u* = f, the scaled solution
+    (1 + eps) u* has global residual exactly eps; the scaled torn pair
+    (1 + eps)(u, lam) has torn residual eps; and a jump delta on one
+    non-owner copy of an edge (star constraints: that copy is in exactly one
+    multiplier) makes r_lam exactly delta there."""
+    u, lam = dd6["u"], dd6["lam"]
+    eps = 1e-6
+    g = oracle.global_residual(c6, (1 + eps) * u)
+    assert np.allclose(g, eps, rtol=1e-6, atol=0)
+    r, rl = oracle.torn_residual(c6, (1 + eps) * u, (1 + eps) * lam)
+    f = c6.torn_rhs()
+    tot = np.sqrt((np.abs(r) ** 2).sum(axis=0) + (np.abs(rl) ** 2).sum(axis=0)) / np.linalg.norm(f, axis=0)
+    assert np.allclose(tot, eps, rtol=1e-6, atol=0)
+    # one non-owner copy: the second entry of multiplier 0
+    a = np.flatnonzero(c6.imap_mult == 0)
+    dom_of = np.searchsorted(c6.imap_ptr, a, side="right") - 1
+    e = a[np.argmax(dom_of)]
+    d = int(dom_of.max())
+    row = sum(c6.domains[i].n for i in range(d)) + int(c6.imap_dof[e])
+    delta = 3e-4 + 1e-4j
+    uj = u.copy()
+    uj[row] += delta
+    r2, rl2 = oracle.torn_residual(c6, uj, lam)
+    jump = rl2 - oracle.torn_residual(c6, u, lam)[1]
+    assert np.allclose(np.abs(jump[0]), abs(delta), rtol=1e-12)
+    assert np.abs(np.delete(jump, 0, axis=0)).max() == 0
+    # the owner-copy global residual does not see a non-owner jump, the torn
+    # residual does
+    assert np.allclose(oracle.global_residual(c6, uj), oracle.global_residual(c6, u), atol=1e-15)
+    # planted mistakes: the conjugate solution and another column's solution
+    assert oracle.global_residual(c6, np.conj(u)).min() > 1e-2
+    assert oracle.global_residual(c6, np.roll(u, 1, axis=1)).min() > 1e-2 if u.shape[1] > 1 else True
+
+
+@pytest.mark.parametrize("name", ["cube6", "cube12", "cube16", "cube18u"])
+def test_condition_estimate_logged(name):
+    """kappa_1 of the test meshes: the FP64 gate (1e-10 error) needs
+    kappa * 2.2e-16 well below it, and err <= kappa * resid turns the
+    residual gates into error bounds.  On cube6 the estimate is checked
+    against the exact dense kappa_1 (onenormest is a lower bound, exact in
+    practice within a small factor)."""
+    c = cached_case(name)
+    k = oracle.cond1_estimate(c.A)
+    print(f"[oracle] {name}: kappa_1 estimate {k:.3e}, kappa * eps64 {k * 2.2e-16:.1e}")
+    assert k * 2.2e-16 < 1e-11
+    if name == "cube6":
+        exact = np.linalg.cond(c.A.toarray(), 1)
+        assert exact / 3 <= k <= exact * (1 + 1e-12), (k, exact)
