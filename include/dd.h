@@ -184,6 +184,25 @@ dd_status dd_workspace_size(dd_ctx ctx, int64_t *bytes);
  * the next bind.  Errors: DD_ERR_NOMEM (too small), DD_ERR_DEVICE. */
 dd_status dd_bind_workspace(dd_ctx ctx, void *dev_ptr, int64_t bytes);
 
+/* Capacity of the static workspace array of dd_bind_static_workspace. */
+#define DD_STATIC_WORKSPACE_BYTES (128LL << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): binds the library's
+ * own static device array of DD_STATIC_WORKSPACE_BYTES (one per GPU, held
+ * until the process ends) as the workspace of ctx, on the current device,
+ * instead of caller memory.  Calls no allocating routine: it uploads the
+ * index tables (synchronous copy) and nothing else; the context's events and
+ * streams are created by its first dd_factor.  Problems whose
+ * dd_workspace_size exceeds the capacity are refused with DD_ERR_NOMEM.
+ * The array is shared by every context bound to it on that GPU and holds
+ * the tables and factors of the context bound last: binding another
+ * context invalidates the previous one (its later calls return
+ * DD_ERR_STATE), and work of two contexts on one GPU's array must not
+ * overlap.  Nothing in it needs clearing: every call writes what it reads.
+ * Errors: DD_ERR_ARG, DD_ERR_NOMEM, DD_ERR_DEVICE. */
+dd_status dd_bind_static_workspace(dd_ctx ctx);
+
 /* Numeric factorisation (section II: the primal DoFs of every domain are
  * eliminated by independent sparse LDL^T factorisations, leaving the dual
  * blocks B_i K_i^-1 B_i^T; their sum, the symmetric block-wise sparse

@@ -53,7 +53,8 @@ class dd_info(C.Structure):
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
            "dd_solve", "dd_get_info", "dd_get_interface_dofs", "dd_get_interface_inverse",
            "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_tune", "dd_solve_subset",
-           "dd_destroy", "dd_last_error"]
+           "dd_bind_static_workspace", "dd_destroy", "dd_last_error"]
+STATIC_WORKSPACE_BYTES = 128 << 20   # DD_STATIC_WORKSPACE_BYTES
 TILE_BUCKETS = 5   # front sizes [0,512) [512,1024) [1024,2048) [2048,4096) [4096,...)
 KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3, "column_update": 4}
 
@@ -74,6 +75,7 @@ def load():
     lib.dd_setup.argtypes = [_P(dd_problem), _P(dd_options), _P(vp)]
     lib.dd_workspace_size.argtypes = [vp, _P(C.c_int64)]
     lib.dd_bind_workspace.argtypes = [vp, vp, C.c_int64]
+    lib.dd_bind_static_workspace.argtypes = [vp]
     lib.dd_factor.argtypes = [vp, vp, vp]
     lib.dd_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp, C.c_int64, vp]
     lib.dd_solve_subset.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, _P(C.c_uint8), vp]
@@ -197,6 +199,17 @@ class Solver:
         self._ws = buf
         self._ws_off = off
         _check(self._lib.dd_bind_workspace(self._ctx, C.c_void_p(buf.data_ptr() + off), self.workspace_bytes))
+        self.device = torch.device(device)
+        return self
+
+    def bind_static(self, device="cuda:0"):
+        """Binds the library's static workspace array of ``device`` (no device
+        allocation; problems above STATIC_WORKSPACE_BYTES are refused).  The
+        array serves the context bound to it last."""
+        import torch
+        torch.cuda.set_device(torch.device(device))
+        _check(self._lib.dd_bind_static_workspace(self._ctx))
+        self._ws = None
         self.device = torch.device(device)
         return self
 

@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # packed FP32 instructions stay disabled in all device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"-I{INC}", f"-I{CSRC}", "-Wno-unused-command-line-argument"]
-SOURCES = ["symbolic.cpp", "schedule_check.cpp", "dd_api.cpp", "kernels.hip"]
+SOURCES = ["symbolic.cpp", "schedule_check.cpp", "dd_api.cpp", "kernels.hip", "static_ws.hip"]
 
 
 def build(verbose: bool = False) -> str:

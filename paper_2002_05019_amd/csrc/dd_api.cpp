@@ -61,9 +61,19 @@ struct dd_ctx_s {
   std::map<std::pair<int, int>, hipGraphExec_t> gsolve;
   // look-ahead of the factorisation: side stream and its two events
   dd::SideStream side;
+  // device whose static workspace array this context is bound to (-1: a
+  // caller-owned workspace)
+  int static_dev = -1;
 };
 
 namespace {
+// context bound last to each device's static workspace array (the array
+// holds that context's tables and factors; an earlier one is refused)
+constexpr int MAX_STATIC_DEV = 64;
+dd_ctx_s *g_static_owner[MAX_STATIC_DEV] = {};
+
+bool static_stale(const dd_ctx_s *c) { return c->static_dev >= 0 && g_static_owner[c->static_dev] != c; }
+
 void drop_graphs(dd_ctx_s *c) {
   for (auto &kv : c->gfactor) (void)hipGraphExecDestroy(kv.second);
   for (auto &kv : c->gsolve) (void)hipGraphExecDestroy(kv.second);
@@ -255,12 +265,11 @@ dd_status dd_workspace_size(dd_ctx c, int64_t *bytes) {
   return DD_OK;
 }
 
-dd_status dd_bind_workspace(dd_ctx c, void *dev, int64_t bytes) {
-  if (!c || !dev) return fail(DD_ERR_ARG, "null argument");
-  if (bytes < c->plan.b_total) return fail(DD_ERR_NOMEM, "workspace smaller than dd_workspace_size");
-  if (((uintptr_t)dev) & 255) return fail(DD_ERR_ARG, "workspace must be 256-byte aligned");
-  HIPCHECK(hipMemcpy((uint8_t *)dev + c->plan.b_meta, c->plan.meta.data(), c->plan.meta.size(),
-                     hipMemcpyHostToDevice));
+}  // extern "C"
+
+namespace {
+// Events and streams of a context (created once, on first need).
+dd_status ensure_runtime(dd_ctx_s *c) {
   if (!c->events) {
     for (int i = 0; i < 4; ++i) HIPCHECK(hipEventCreate(&c->ev[i]));
     c->events = true;
@@ -276,16 +285,59 @@ dd_status dd_bind_workspace(dd_ctx c, void *dev, int64_t bytes) {
     c->side.fork = e0;
     c->side.join = e1;
   }
+  return DD_OK;
+}
+
+// Uploads the index tables into the workspace and makes it the context's.
+dd_status bind_region(dd_ctx_s *c, void *dev, int64_t bytes, int static_dev) {
+  HIPCHECK(hipMemcpy((uint8_t *)dev + c->plan.b_meta, c->plan.meta.data(), c->plan.meta.size(),
+                     hipMemcpyHostToDevice));
   drop_graphs(c);
+  if (c->static_dev >= 0 && g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+  c->static_dev = static_dev;
+  if (static_dev >= 0) g_static_owner[static_dev] = c;
   c->ws = (uint8_t *)dev;
   c->ws_bytes = bytes;
   c->factored = false;
+  c->fact_rec = c->solve_rec = false;
+  c->status_read = false;
   return DD_OK;
+}
+}  // namespace
+
+namespace dd {
+// Binds device `device`'s static workspace array (address dev, capacity
+// bytes); called by dd_bind_static_workspace, which owns the array.
+dd_status bind_static(dd_ctx c, void *dev, int64_t bytes, int device) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  if (device < 0 || device >= MAX_STATIC_DEV) return fail(DD_ERR_DEVICE, "device id out of range");
+  if (c->plan.b_total > bytes)
+    return fail(DD_ERR_NOMEM, "workspace of " + std::to_string(c->plan.b_total) +
+                                  " bytes exceeds the static workspace array (" + std::to_string(bytes) + " bytes)");
+  return bind_region(c, dev, bytes, device);
+}
+dd_status set_error(dd_status s, const char *msg) { return fail(s, msg); }
+}  // namespace dd
+
+extern "C" {
+
+dd_status dd_bind_workspace(dd_ctx c, void *dev, int64_t bytes) {
+  if (!c || !dev) return fail(DD_ERR_ARG, "null argument");
+  if (bytes < c->plan.b_total) return fail(DD_ERR_NOMEM, "workspace smaller than dd_workspace_size");
+  if (((uintptr_t)dev) & 255) return fail(DD_ERR_ARG, "workspace must be 256-byte aligned");
+  const dd_status r = ensure_runtime(c);
+  if (r != DD_OK) return r;
+  return bind_region(c, dev, bytes, -1);
 }
 
 dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
   if (!c) return fail(DD_ERR_ARG, "null context");
   if (!c->ws) return fail(DD_ERR_STATE, "no workspace bound");
+  if (static_stale(c)) return fail(DD_ERR_STATE, "the static workspace array was bound to another context");
+  {
+    const dd_status r = ensure_runtime(c);
+    if (r != DD_OK) return r;
+  }
   if (!vals && c->plan.nnz_total > 0) return fail(DD_ERR_ARG, "vals is null");
   hipStream_t st = (hipStream_t)stream;
   const void *v = vals;
@@ -314,6 +366,7 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
 dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, int64_t ldu, dd_z *lam, int64_t ldl,
                    void *stream) {
   if (!c) return fail(DD_ERR_ARG, "null context");
+  if (static_stale(c)) return fail(DD_ERR_STATE, "the static workspace array was bound to another context");
   if (!c->factored) return fail(DD_ERR_STATE, "dd_solve before dd_factor");
   if (nrhs < 0) return fail(DD_ERR_ARG, "nrhs < 0");
   if (nrhs == 0) return DD_OK;
@@ -412,6 +465,7 @@ dd_status dd_solve_subset(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd
     return fail(DD_ERR_ARG, "subset recovery needs the FP64 path (refinement uses every domain's solution)");
   if (nrhs < 0) return fail(DD_ERR_ARG, "nrhs < 0");
   if (!domain_mask) return fail(DD_ERR_ARG, "domain_mask is null");
+  if (static_stale(c)) return fail(DD_ERR_STATE, "the static workspace array was bound to another context");
   if (!c->factored) return fail(DD_ERR_STATE, "dd_solve_subset before dd_factor");
   if (nrhs == 0) return DD_OK;
   if (!f || !u) return fail(DD_ERR_ARG, "f or u is null");
@@ -476,7 +530,7 @@ dd_status dd_get_info(dd_ctx c, dd_info *info) {
       info->t_solve = ms * 1e-3;
     }
   }
-  if (c->ws && c->factored) {
+  if (c->ws && c->factored && !static_stale(c)) {
     HIPCHECK(hipStreamSynchronize(c->last));
     HIPCHECK(read_status(c));
     info->n_perturbed = c->stat[0];
@@ -500,6 +554,7 @@ dd_status dd_get_interface_dofs(dd_ctx c, int32_t dom, int32_t *count, int32_t *
 dd_status dd_get_interface_inverse(dd_ctx c, int32_t dom, dd_z *out, void *stream) {
   if (!c || !out) return fail(DD_ERR_ARG, "null argument");
   if (dom < 0 || dom >= c->plan.n_dom) return fail(DD_ERR_ARG, "domain out of range");
+  if (static_stale(c)) return fail(DD_ERR_STATE, "the static workspace array was bound to another context");
   if (!c->factored) return fail(DD_ERR_STATE, "no factorisation");
   int f = c->plan.gamma_front[dom];
   if (f < 0) return fail(DD_ERR_ARG, "domain has no interface");
@@ -547,6 +602,11 @@ dd_status dd_kernel_timer_read(dd_ctx c, double *seconds, int64_t *launches, dou
 dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
   if (!c) return fail(DD_ERR_ARG, "null context");
   if (!c->ws) return fail(DD_ERR_STATE, "no workspace bound");
+  if (static_stale(c)) return fail(DD_ERR_STATE, "the static workspace array was bound to another context");
+  {
+    const dd_status r = ensure_runtime(c);
+    if (r != DD_OK) return r;
+  }
   try {
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -617,6 +677,7 @@ dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
 
 void dd_destroy(dd_ctx c) {
   if (!c) return;
+  if (c->static_dev >= 0 && g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
   if (c->events)
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->ev[i]);
   for (auto &e : c->tev) (void)hipEventDestroy(e);
