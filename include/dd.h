@@ -115,8 +115,9 @@ typedef struct {
     int32_t leaf_size;     /* nested-dissection leaf size (default 48)          */
     int32_t use_graph;     /* 1: capture the factorisation (per value pointer)
                               and the solve core (per column count) into
-                              hipGraphs on first use and replay them; 0: plain
-                              launches.  Timed kernels always run plain.       */
+                              hipGraphs on first use and replay them; 2: the
+                              solve core only; 0: plain launches.  Timed
+                              kernels always run plain.                       */
     int32_t verbose;       /* print the symbolic summary to stderr              */
     int32_t schur_tile[DD_TILE_BUCKETS];
                            /* output tile edge of the trailing Schur update per

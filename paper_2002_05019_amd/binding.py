@@ -68,6 +68,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2002_05019_amd.build`")
+    # torch brings its own HIP runtime; loading it first makes the library
+    # resolve libamdhip64 to that same runtime, so that torch's device
+    # pointers and streams are valid in the library (a second runtime
+    # loaded from the system path would not see the device)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     lib.dd_default_options.argtypes = [_P(dd_options)]
@@ -155,7 +160,7 @@ class Solver:
         opt.refine_tol = float(refine_tol)
         opt.refine_maxit = int(refine_maxit)
         opt.verbose = int(bool(verbose))
-        opt.use_graph = int(bool(use_graph))
+        opt.use_graph = 2 if use_graph == "solve" else int(bool(use_graph))
         opt.verify_schedule = int(bool(verify_schedule))
         if schur_tile is not None:
             assert len(schur_tile) == TILE_BUCKETS

@@ -185,7 +185,7 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
     if (o.leaf_size < 1) return fail(DD_ERR_ARG, "leaf_size must be >= 1");
     if (o.refine_maxit < 0) return fail(DD_ERR_ARG, "refine_maxit must be >= 0");
     if (!(o.refine_tol > 0)) return fail(DD_ERR_ARG, "refine_tol must be > 0");
-    if (o.use_graph != 0 && o.use_graph != 1) return fail(DD_ERR_ARG, "use_graph must be 0 or 1");
+    if (o.use_graph < 0 || o.use_graph > 2) return fail(DD_ERR_ARG, "use_graph must be 0, 1 or 2");
     for (int b = 0; b < DD_TILE_BUCKETS; ++b)
       if (o.schur_tile[b] != 0 && o.schur_tile[b] != 64 && o.schur_tile[b] != 128)
         return fail(DD_ERR_ARG, "schur_tile entries must be 0, 64 or 128");
@@ -223,6 +223,7 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
     }
     if (so.verify) {
       m = dd::check_schedule(c->plan, c->plan.factor_seq);
+      if (m.empty()) m = dd::check_layout(c->plan);
       if (!m.empty()) {
         delete c;
         return fail(DD_ERR_STATE, "stream schedule check: " + m);
@@ -344,7 +345,7 @@ dd_status dd_factor(dd_ctx c, const dd_z *vals, void *stream) {
   // FP64 copy of the operator for the refinement residuals
   if (c->plan.precision != 0) HIPCHECK(dd::operator_copy(c->plan, c->ws, vals, st));
   HIPCHECK(hipEventRecord(c->ev[0], st));
-  if (c->opt.use_graph && c->tm.kind < 0) {
+  if (c->opt.use_graph == 1 && c->tm.kind < 0) {
     auto it = c->gfactor.find(v);
     if (it == c->gfactor.end()) {
       hipGraphExec_t ge;
@@ -660,6 +661,7 @@ dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
     if (!m.empty()) return fail(DD_ERR_PATTERN, m);
     if (so.verify) {
       m = dd::check_schedule(np, np.factor_seq);
+      if (m.empty()) m = dd::check_layout(np);
       if (!m.empty()) return fail(DD_ERR_STATE, "stream schedule check: " + m);
     }
     if (np.b_total != c->plan.b_total || np.b_meta != c->plan.b_meta || np.meta.size() != c->plan.meta.size())

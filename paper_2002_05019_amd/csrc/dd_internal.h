@@ -1,10 +1,14 @@
 // Internal data layout shared by the host planner and the HIP kernels.
 //
-// Every front (dense frontal matrix of the multifrontal LDL^T) is stored
+// Every front (dense frontal matrix of the multifrontal LDL^T) is factored
 // column-major, planar complex: the real plane at `off`, the imaginary plane
 // at `off + n*n` (elements of the factor precision T).  Only the lower
 // triangle is meaningful; after the pivot-tile factorisation the strict lower
-// triangle of every diagonal NB x NB tile holds L11^-1 (not L11).
+// triangle of every diagonal NB x NB tile holds L11^-1 (not L11).  The full
+// front lives only while it is factored and until its parent has gathered
+// its update block; its first s columns (the factor) are then kept at `loff`
+// (real plane n x s, imaginary plane after it) unless the front has no
+// update block (loff = off).
 #pragma once
 #include <cstdint>
 
@@ -23,7 +27,11 @@ constexpr int ZMMA_MIN = 8;   // above this many right-hand sides they run on MF
 enum FrontKind : int32_t { FK_INTERIOR = 0, FK_GAMMA = 1, FK_AUX = 2 };
 
 struct FrontDev {
-  int64_t off;     // front matrix (T elements), ld = n
+  int64_t off;     // front matrix (T elements), ld = n, imaginary plane at off + n*n;
+                   // while the front's level (and its parent's) is factored
+  int64_t loff;    // stored factor read by the solves: columns [0, s) with ld n,
+                   // imaginary plane at loff + lpim (FK_GAMMA: -1, the solves use X)
+  int64_t lpim;
   int64_t woff;    // W scratch (T elements): re plane [n x wcols], im plane after it
   int64_t soff;    // index of fully-summed position 0 in the side arrays
   int64_t voff;    // solve vector (T elements): re plane [n x max_rhs], im after it

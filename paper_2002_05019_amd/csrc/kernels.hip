@@ -487,6 +487,36 @@ __global__ __launch_bounds__(256) void k_auxg(KP<T> p, int64_t first) {
   }
 }
 
+// Stored factor: columns [c0, c0 + 16) of front f on rows [r0, r0 + 256),
+// from the full front matrix (ld n) to the stored-factor place (ld n,
+// imaginary plane at loff + lpim), whose memory outlives the front.
+template <typename T>
+__global__ __launch_bounds__(256) void k_store(KP<T> p, int64_t first) {
+  const Item it = p.items[first + blockIdx.x];
+  const FrontDev f = p.F[it.f];
+  const int n = f.n, r = it.i + threadIdx.x, c0 = it.k;
+  if (r >= n) return;
+  const int cend = min(c0 + 16, f.s);
+  const T *sr = p.num + f.off;
+  const T *si = sr + (int64_t)n * n;
+  T *dr = p.num + f.loff;
+  T *di = dr + f.lpim;
+  T xr[16], xi[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int64_t o = r + (int64_t)min(c0 + u, cend - 1) * n;
+    xr[u] = sr[o];
+    xi[u] = si[o];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+    if (c0 + u < cend) {
+      const int64_t o = r + (int64_t)(c0 + u) * n;
+      dr[o] = xr[u];
+      di[o] = xi[u];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pivot tile: restricted Bunch-Kaufman LDL^T of the NB x NB diagonal tile in
 // FP64, with L^-1 formed alongside (section II: pivot search confined to the
@@ -1663,8 +1693,8 @@ __global__ __launch_bounds__(256) void k_ffront(KP<T> p, int64_t first, int nrhs
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
+  const T *fr = p.num + f.loff;   // stored factor
+  const T *fi = fr + f.lpim;
   {
     const bool aux = f.kind == FK_AUX;
     const int64_t ld = aux ? p.n_mult : p.n_torn;
@@ -1723,8 +1753,8 @@ __global__ __launch_bounds__(256) void k_bfront(KP<T> p, int64_t first, int nrhs
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
+  const T *fr = p.num + f.loff;   // stored factor
+  const T *fi = fr + f.lpim;
   const bool aux = f.kind == FK_AUX;
   const int64_t ld = aux ? p.n_mult : p.n_torn;
   {
@@ -1842,8 +1872,8 @@ __global__ __launch_bounds__(256) void k_zq_n(KP<T> p, int64_t first, int nrhs) 
   const int cend = min(c0 + ZKC, M == 0 ? min(s, i0 + 64) : s);
   const int rlim = M == 0 ? s : n;
   const int64_t mr = p.mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
+  const T *fr = p.num + f.loff;   // stored factor
+  const T *fi = fr + f.lpim;
   const T *inr = M == 0 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
   const int32_t *pm = p.perm + f.soff;
@@ -1905,8 +1935,8 @@ __global__ __launch_bounds__(256) void k_zq_t(KP<T> p, int64_t first, int nrhs) 
   const int n = f.n, s = f.s, i0 = it.i, k0 = it.j, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int kend = min(k0 + ZKC, M == 2 ? n : s);
   const int64_t mr = p.mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
+  const T *fr = p.num + f.loff;   // stored factor
+  const T *fi = fr + f.lpim;
   const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
   T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
@@ -1988,8 +2018,8 @@ __global__ __launch_bounds__(256, 3) void k_zmma_n(KP<T> p, int64_t first, int n
   const int cend = min(c0 + ZKC, M == 0 ? min(s, i0 + 64) : s);
   const int rlim = M == 0 ? s : n;
   const int64_t mr = p.mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
+  const T *fr = p.num + f.loff;   // stored factor
+  const T *fi = fr + f.lpim;
   const T *inr = M == 0 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
   const int32_t *pm = p.perm + f.soff;
@@ -2031,8 +2061,8 @@ __global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs
   const int n = f.n, s = f.s, i0 = it.i, k0 = it.j;
   const int kend = min(k0 + ZKC, M == 2 ? n : s);
   const int64_t mr = p.mr;
-  const T *fr = p.num + f.off;
-  const T *fi = fr + (int64_t)n * n;
+  const T *fr = p.num + f.loff;   // stored factor
+  const T *fi = fr + f.lpim;
   const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
   T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
@@ -2663,6 +2693,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
       case L_DINVZ: hipLaunchKernelGGL(k_dinvz<T>, g, b, 0, st, k, L.first); break;
+      case L_STORE: hipLaunchKernelGGL(k_store<T>, g, b, 0, st, k, L.first); break;
       case L_INVSYRK: hipLaunchKernelGGL(k_invsyrk<T>, g, b, 0, st, k, L.first); break;
       case S_FINIT: hipLaunchKernelGGL(k_finit<T>, g, b, 0, st, k, L.first, nrhs); break;
       case S_FFIN: hipLaunchKernelGGL(k_ffin<T>, g, b, 0, st, k, L.first, nrhs); break;

@@ -26,6 +26,7 @@ enum LaunchKind : int32_t {
   L_FORK,       // the side stream waits for the main stream (no kernel)
   L_JOIN,       // the main stream waits for the side stream (no kernel)
   L_DINVZ,      // Y = D^-1 Z of an interface root, stored transposed above Z
+  L_STORE,      // factor columns of a front into its stored-factor place
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)
@@ -133,6 +134,13 @@ struct Plan {
   Launch tune[TILE_BUCKETS][2] = {};
   size_t elem = 8;                     // sizeof(T)
   int64_t t_elems = 0;                 // T elements in the numeric region
+  // numeric region (T elements): stored factors, W scratch of the widest
+  // level, and the arena (peak of the factorisation's live fronts, or the
+  // solve's vectors, whichever is larger)
+  int64_t e_stored = 0, e_w = 0, e_arena_factor = 0, e_arena_solve = 0;
+  // factorisation level of every front and the last level that reads its
+  // full matrix (its parent's); the layout check replays them
+  std::vector<int32_t> front_lev, front_last;
   int64_t vf_off = 0, vx_off = 0, vd_off = 0, vl_off = 0, vc_off = 0, part_off = 0;
   int64_t side_n = 0;                  // fully-summed positions (side arrays)
   // byte offsets inside the workspace
@@ -185,5 +193,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &plan);
 // "" if every pair of launches of `seq` on different streams that the
 // fork / join points leave unordered touches disjoint data, else a message
 std::string check_schedule(const Plan &P, const std::vector<Launch> &seq);
+// "" if the numeric layout is consistent: the full matrices of fronts alive
+// at the same level (from their own level to their parent's) are disjoint,
+// the stored factors and interface inverses are disjoint from each other and
+// lie below the W scratch, and the W buffers of one level are disjoint
+std::string check_layout(const Plan &P);
 
 }  // namespace dd

@@ -149,4 +149,53 @@ std::string check_schedule(const Plan &P, const std::vector<Launch> &seq) {
   return std::string();
 }
 
+std::string check_layout(const Plan &P) {
+  const int nf = (int)P.fronts.size();
+  if ((int)P.front_lev.size() != nf || (int)P.front_last.size() != nf) return "layout: levels missing";
+  using R = std::pair<int64_t, int64_t>;   // [begin, end) in T elements
+  auto overlap = [](std::vector<std::pair<R, int>> v, const char *what) -> std::string {
+    std::sort(v.begin(), v.end());
+    for (size_t i = 1; i < v.size(); ++i)
+      if (v[i].first.first < v[i - 1].first.second)
+        return std::string("layout: ") + what + " of fronts " + std::to_string(v[i - 1].second) + " and " +
+               std::to_string(v[i].second) + " overlap";
+    return std::string();
+  };
+  // stored factors and interface inverses: disjoint, below the W scratch
+  std::vector<std::pair<R, int>> st;
+  for (int f = 0; f < nf; ++f) {
+    const FrontDev &d = P.fronts[f];
+    if (d.kind == FK_GAMMA) st.push_back({{d.xoff, d.xoff + 2 * (int64_t)d.s * d.s}, f});
+    else st.push_back({{d.loff, d.loff + d.lpim + (d.lpim == (int64_t)d.n * d.n ? (int64_t)d.n * d.n : (int64_t)d.n * d.s)}, f});
+  }
+  std::string m = overlap(st, "stored factors");
+  if (!m.empty()) return m;
+  for (auto &x : st)
+    if (x.first.first < 0 || x.first.second > P.e_stored) return "layout: stored factor outside its region";
+  int nlev = 0;
+  for (int f = 0; f < nf; ++f) nlev = std::max(nlev, P.front_last[f] + 1);
+  for (int l = 0; l < nlev; ++l) {
+    std::vector<std::pair<R, int>> live, w;
+    for (int f = 0; f < nf; ++f) {
+      const FrontDev &d = P.fronts[f];
+      if (P.front_lev[f] == l) {
+        const int64_t wb = (((2 * (int64_t)d.n * d.wcols) + 63) & ~(int64_t)63) + d.wstride;
+        w.push_back({{d.woff, d.woff + wb}, f});
+        if (d.woff < P.e_stored || d.woff + wb > P.e_stored + P.e_w) return "layout: W outside its region";
+      }
+      if (P.front_lev[f] > l || P.front_last[f] < l) continue;
+      if (d.loff == d.off && d.kind != FK_GAMMA) continue;   // kept whole: a stored factor
+      const int64_t arena = P.e_stored + P.e_w;
+      const R r{d.off, d.off + 2 * (int64_t)d.n * d.n};
+      if (r.first < arena || r.second > arena + P.e_arena_factor) return "layout: front outside the arena";
+      live.push_back({r, f});
+    }
+    m = overlap(live, ("live front matrices at level " + std::to_string(l)).c_str());
+    if (!m.empty()) return m;
+    m = overlap(w, ("W scratch at level " + std::to_string(l)).c_str());
+    if (!m.empty()) return m;
+  }
+  return std::string();
+}
+
 }  // namespace dd

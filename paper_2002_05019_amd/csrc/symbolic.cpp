@@ -819,26 +819,145 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.bytes_solve = 2.0 * fb;
 
   // ------------------------------------------------------------ numeric layout (T elements)
+  // Factor order: domain levels by height, the interface roots, auxiliary
+  // levels by height (the schedule below uses the same grouping).
+  auto by_height = [&](int kind_lo, int kind_hi, bool include_gamma) {
+    std::map<int, std::vector<int>> lv;
+    for (int f = 0; f < nf; ++f) {
+      int k = P.fronts[f].kind;
+      if (k == FK_GAMMA && !include_gamma) continue;
+      if (k < kind_lo || k > kind_hi) continue;
+      lv[F[f].height].push_back(f);
+    }
+    std::vector<std::vector<int>> out;
+    for (auto &kv : lv) out.push_back(kv.second);
+    return out;
+  };
+  std::vector<std::vector<int>> dom_levels = by_height(FK_INTERIOR, FK_INTERIOR, false);
+  std::vector<int> gam;
+  for (int i = 0; i < p.n_dom; ++i)
+    if (P.gamma_front[i] >= 0) gam.push_back(P.gamma_front[i]);
+  // domains without interface: their roots are interior fronts already
+  std::vector<std::vector<int>> aux_levels = by_height(FK_AUX, FK_AUX, false);
+  std::vector<std::vector<int>> levels(dom_levels);
+  if (!gam.empty()) levels.push_back(gam);
+  levels.insert(levels.end(), aux_levels.begin(), aux_levels.end());
+  const int nlev = (int)levels.size();
+  std::vector<int> lev(nf, -1);
+  for (int l = 0; l < nlev; ++l)
+    for (int f : levels[l]) lev[f] = l;
+  for (int f = 0; f < nf; ++f)
+    if (lev[f] < 0) return "internal: front without a level";
+  // a front's full matrix is read by its own level and by its parent's
+  // (extend-add of the update block)
+  std::vector<int> last_use(nf);
+  for (int f = 0; f < nf; ++f) {
+    last_use[f] = F[f].parent >= 0 ? lev[F[f].parent] : lev[f];
+    if (last_use[f] < lev[f]) return "internal: parent factored before its child";
+  }
+  P.front_lev = lev;
+  P.front_last = last_use;
+  // fronts whose full matrix is kept as the stored factor (no update block);
+  // interface roots keep only the interface inverse X
+  auto kept = [&](int f) { return P.fronts[f].kind != FK_GAMMA && P.fronts[f].n == P.fronts[f].s; };
+
   const int64_t mr = P.max_rhs;
   int64_t at = 0;
   auto align = [](int64_t x) { return (x + 63) & ~(int64_t)63; };
+  // 1. stored factors (alive from their factorisation to the next one)
   for (int f = 0; f < nf; ++f) {
     FrontDev &d = P.fronts[f];
-    d.off = at;
-    at = align(at + 2 * (int64_t)d.n * d.n);
+    if (d.kind == FK_GAMMA) {
+      d.xoff = at;
+      at = align(at + 2 * (int64_t)d.s * d.s);
+      d.loff = -1;
+      d.lpim = 0;
+    } else if (kept(f)) {
+      d.off = d.loff = at;
+      d.lpim = (int64_t)d.n * d.n;
+      at = align(at + 2 * (int64_t)d.n * d.n);
+    } else {
+      d.loff = at;
+      d.lpim = (int64_t)d.n * d.s;
+      at = align(at + 2 * (int64_t)d.n * d.s);
+    }
   }
-  for (int f = 0; f < nf; ++f) {
-    FrontDev &d = P.fronts[f];
-    d.woff = at;
-    const int64_t wbuf = align(2 * (int64_t)d.n * d.wcols);
-    d.wstride = d.s > KBLK ? wbuf : 0;   // second buffer for odd outer blocks
-    at = align(at + wbuf + d.wstride);
+  P.e_stored = at;
+  // 2. W scratch: the fronts of one level at a time (factorisation and solve
+  // work on one level after the other)
+  {
+    const int64_t wbase = at;
+    int64_t wmax = 0;
+    for (int l = 0; l < nlev; ++l) {
+      int64_t o = 0;
+      for (int f : levels[l]) {
+        FrontDev &d = P.fronts[f];
+        d.woff = wbase + o;
+        const int64_t wbuf = align(2 * (int64_t)d.n * d.wcols);
+        d.wstride = d.s > KBLK ? wbuf : 0;   // second buffer for odd outer blocks
+        o = align(o + wbuf + d.wstride);
+      }
+      wmax = std::max(wmax, o);
+    }
+    at = wbase + wmax;
+    P.e_w = wmax;
   }
+  // 3. arena.  During a factorisation it holds the full front matrices, each
+  // from its level to its parent's (first fit over the level sequence);
+  // during a solve, the solve's vectors (the fronts are dead by then).
+  const int64_t arena = at;
+  {
+    std::vector<std::pair<int64_t, int64_t>> freel;   // (start, length), by start
+    int64_t top = 0;
+    auto take = [&](int64_t len) {
+      for (size_t i = 0; i < freel.size(); ++i)
+        if (freel[i].second >= len) {
+          const int64_t o = freel[i].first;
+          freel[i].first += len;
+          freel[i].second -= len;
+          if (freel[i].second == 0) freel.erase(freel.begin() + (long)i);
+          return o;
+        }
+      const int64_t o = top;
+      top += len;
+      return o;
+    };
+    auto give = [&](int64_t o, int64_t len) {
+      auto it = std::lower_bound(freel.begin(), freel.end(), std::make_pair(o, (int64_t)0));
+      it = freel.insert(it, {o, len});
+      size_t i = (size_t)(it - freel.begin());
+      if (i + 1 < freel.size() && freel[i].first + freel[i].second == freel[i + 1].first) {
+        freel[i].second += freel[i + 1].second;
+        freel.erase(freel.begin() + (long)i + 1);
+      }
+      if (i > 0 && freel[i - 1].first + freel[i - 1].second == freel[i].first) {
+        freel[i - 1].second += freel[i].second;
+        freel.erase(freel.begin() + (long)i);
+      }
+      if (!freel.empty() && freel.back().first + freel.back().second == top) {
+        top = freel.back().first;
+        freel.pop_back();
+      }
+    };
+    int64_t peak = 0;
+    std::vector<std::vector<int>> dies(nlev);
+    for (int f = 0; f < nf; ++f)
+      if (!kept(f)) dies[last_use[f]].push_back(f);
+    for (int l = 0; l < nlev; ++l) {
+      std::vector<int> fs;
+      for (int f : levels[l])
+        if (!kept(f)) fs.push_back(f);
+      std::stable_sort(fs.begin(), fs.end(), [&](int a, int b) { return P.fronts[a].n > P.fronts[b].n; });
+      for (int f : fs) P.fronts[f].off = arena + take(align(2 * (int64_t)P.fronts[f].n * P.fronts[f].n));
+      peak = std::max(peak, top);
+      for (int f : dies[l]) give(P.fronts[f].off - arena, align(2 * (int64_t)P.fronts[f].n * P.fronts[f].n));
+    }
+    P.e_arena_factor = peak;
+  }
+  at = arena;   // the solve's vectors, from the start of the arena
   for (int f = 0; f < nf; ++f) {
     FrontDev &d = P.fronts[f];
     if (d.kind != FK_GAMMA) continue;
-    d.xoff = at;
-    at = align(at + 2 * (int64_t)d.s * d.s);
     d.goff = at;
     at = align(at + 4 * (int64_t)d.s * mr);
   }
@@ -1129,18 +1248,6 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     push(seq, L_SCAT, sc);
     push(seq, L_AUXG, ag);
   };
-  auto by_height = [&](int kind_lo, int kind_hi, bool include_gamma) {
-    std::map<int, std::vector<int>> lv;
-    for (int f = 0; f < nf; ++f) {
-      int k = P.fronts[f].kind;
-      if (k == FK_GAMMA && !include_gamma) continue;
-      if (k < kind_lo || k > kind_hi) continue;
-      lv[F[f].height].push_back(f);
-    }
-    std::vector<std::vector<int>> out;
-    for (auto &kv : lv) out.push_back(kv.second);
-    return out;
-  };
   // Z = L11^-1 of the fully-summed block (P basis) by recursive halving of
   // the tile range; all splits of one height (over all fronts) form one pair
   // of launches.  The single tiles already hold L_kk^-1.
@@ -1176,18 +1283,26 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       if (zfront(f)) z.push_back(f);
     return z;
   };
-  std::vector<std::vector<int>> dom_levels = by_height(FK_INTERIOR, FK_INTERIOR, false);
-  std::vector<int> gam;
-  for (int i = 0; i < p.n_dom; ++i)
-    if (P.gamma_front[i] >= 0) gam.push_back(P.gamma_front[i]);
-  // domains without interface: their roots are interior fronts already
-  std::vector<std::vector<int>> aux_levels = by_height(FK_AUX, FK_AUX, false);
+  // the factor columns of the level's fronts (except those kept whole) into
+  // their stored-factor place: 16 columns x 256 rows per item, from the
+  // columns' 64-row diagonal tile down (the solves read nothing above it)
+  auto store = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
+    std::vector<Item> st;
+    for (int f : fs) {
+      const FrontDev &d = P.fronts[f];
+      if (d.kind == FK_GAMMA || kept(f)) continue;
+      for (int c0 = 0; c0 < d.s; c0 += 16)
+        for (int r0 = (c0 / NB) * NB; r0 < d.n; r0 += 256) st.push_back({f, c0, r0, 0});
+    }
+    push(seq, L_STORE, st);
+  };
 
   // factor
   for (auto &lv : dom_levels) {
     assemble(P.factor_seq, lv, false);
     factor_steps(P.factor_seq, lv);
     zsteps(P.factor_seq, zset(lv));
+    store(P.factor_seq, lv);
   }
   if (!gam.empty()) {
     assemble(P.factor_seq, gam, false);
@@ -1207,6 +1322,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     assemble(P.factor_seq, lv, true);
     factor_steps(P.factor_seq, lv);
     zsteps(P.factor_seq, zset(lv));
+    store(P.factor_seq, lv);
   }
   P.items.resize(P.items.size() + item_pad, Item{0, 0, 0, 0});
   // tuner launches: first outer block's trailing update of every front of a
@@ -1315,7 +1431,8 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.max_partials = max_part;
   P.part_off = at;
   at = align(at + std::max<int64_t>(1, max_part) * NB * mr * 2);
-  P.t_elems = at;
+  P.e_arena_solve = at - arena;
+  P.t_elems = arena + std::max(P.e_arena_factor, P.e_arena_solve);
 
   // ------------------------------------------------------------ meta blob
   auto put = [&](const void *src, size_t bytes) -> int64_t {
@@ -1375,6 +1492,12 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.b_total = b;
 
   if (o.verbose) {
+    // workspace breakdown (GB)
+    const double e = (double)P.elem / 1e9;
+    fprintf(stderr, "[dd] workspace GB: stored factors %.3f, W %.3f, arena %.3f (fronts %.3f, solve vectors %.3f), "
+                    "meta %.3f side %.3f r64 %.3f\n",
+            P.e_stored * e, P.e_w * e, std::max(P.e_arena_factor, P.e_arena_solve) * e, P.e_arena_factor * e,
+            P.e_arena_solve * e, P.meta.size() / 1e9, P.side_n * 40 / 1e9, (P.b_status - P.b_vals) / 1e9);
     fprintf(stderr,
             "[dd] domains %d torn %lld mult %lld | fronts dom %d (max %d) aux %d (max %d) blocks %d\n"
             "[dd] factor %.3e flop, solve %.3e flop/rhs, factors %.3f GB | workspace %.3f GB | launches factor %zu solve %zu\n",

@@ -49,3 +49,29 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr), r.stdout + r.stderr
+
+
+def test_global_direct_model():
+    """The footprint model of the undecomposed sparse direct factor that the
+    memory record compares against: every non-PEC edge (3 n (n-1)^2 of an n^3
+    PEC cube) is eliminated exactly once, the 6^3 and 48^3 figures are the
+    closed-form recursion's (4.44e6 flop; 2.21e8 factor entries = 3.54 GB in
+    complex FP64, 2.46e12 flop), and SuperLU's own ordering of the same
+    matrix lands in the same range (nnz(L + U) / 2 against the model's
+    symmetric factor)."""
+    import scipy.sparse.linalg as spl
+
+    from tests.conftest import cached_case
+    for n in (4, 6, 12, 24, 48):
+        assert bench.global_direct_model(n)["eliminated"] == 3 * n * (n - 1) ** 2
+    m6 = bench.global_direct_model(6)
+    assert abs(m6["fma"] * 8 - 4.4394e6) < 1e3
+    m48 = bench.global_direct_model(48)
+    assert m48["nnz"] == 221021208
+    assert abs(m48["fma"] * 8 / 2.4607e12 - 1) < 1e-3
+    for name, n in (("cube12", 12), ("cube16", 16)):
+        A = cached_case(name).A.tocsc()
+        lu = spl.splu(A)
+        ratio = (lu.L.nnz + lu.U.nnz) / 2 / bench.global_direct_model(n)["nnz"]
+        print(f"[model] {name}: SuperLU nnz(L+U)/2 over the model's nnz(L): {ratio:.2f}")
+        assert 0.5 < ratio < 4

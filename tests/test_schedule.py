@@ -3,7 +3,10 @@
 The factorisation overlaps its latency-bound pivot chain with the trailing
 update on a side stream.  ``verify_schedule`` replays the plan's fork / join points and fails
 ``dd_setup`` if two launches that those leave unordered touch the same front
-data with at least one write."""
+data with at least one write.  It also checks the memory plan: fronts share
+one arena, each alive from its own level to its parent's (which gathers its
+update block), so the full matrices of fronts alive at the same level must be
+disjoint, and the stored factors must not overlap each other."""
 import pytest
 
 from paper_2002_05019_amd.binding import Solver
