@@ -127,8 +127,14 @@ typedef struct {
                            /* 1: dd_setup (and dd_tune's re-plan) also checks
                               on the host that the factorisation's launches on
                               its side streams never touch data that an
-                              unordered launch writes (DD_ERR_STATE if they
-                              do); costs host time, for tests               */
+                              unordered launch writes, and that fronts alive
+                              at the same time do not share memory
+                              (DD_ERR_STATE if they do); costs host time   */
+    const char *tune_cache;/* optional path of dd_tune's tile cache (a text
+                              file, one line per problem shape and device:
+                              key and the five tile edges); dd_tune reads its
+                              line instead of measuring, or appends one after
+                              measuring.  Copied by dd_setup; NULL: none    */
 } dd_options;
 
 typedef struct {
@@ -158,7 +164,8 @@ typedef struct {
                                pivot, n_dom for the auxiliary matrix, -1 none   */
     int32_t n_pivot_2x2;    /* 2 x 2 pivots chosen by the last dd_factor        */
     int32_t n_interchanges; /* pivot interchanges inside the pivot tiles         */
-    int32_t reserved_;
+    int32_t tuned_from_cache; /* 1 if the last dd_tune took its tiles from the
+                               tune_cache file                                   */
 } dd_info;
 
 /* Defaults listed above. */
@@ -290,7 +297,9 @@ dd_status dd_kernel_timer_read(dd_ctx ctx, double *seconds, int64_t *launches, d
 
 /* Tile autotuner for the batched factorisation of uneven fronts (section II
  * builds the method on many independent dense operations, to expose
- * concurrency for parallel and GPU processing): for every front-size bucket
+ * concurrency for parallel and GPU processing).  With a tune_cache whose
+ * line matches this problem's front shapes, precision and device, its tiles
+ * are used without measuring.  Otherwise, for every front-size bucket
  * that has fronts, times the first
  * outer block's Schur update of all its fronts with 64 x 64 and 128 x 128
  * tiles on the bound workspace (a few launches each, events on hip_stream),
@@ -302,6 +311,8 @@ dd_status dd_kernel_timer_read(dd_ctx ctx, double *seconds, int64_t *launches, d
  * discarded).  Synchronises hip_stream.
  * Errors: DD_ERR_STATE (no workspace), DD_ERR_DEVICE. */
 dd_status dd_tune(dd_ctx ctx, int32_t *schur_tile, void *hip_stream);
+/* (The cache line is appended after the measurement; a cache file that
+ * cannot be read or written is ignored.) */
 
 /* Releases the context (host state only; the workspace stays caller-owned). */
 void dd_destroy(dd_ctx ctx);

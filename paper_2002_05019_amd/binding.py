@@ -37,7 +37,7 @@ class dd_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("refine_tol", C.c_double), ("refine_maxit", C.c_int32),
                 ("max_rhs", C.c_int32), ("leaf_size", C.c_int32), ("use_graph", C.c_int32),
                 ("verbose", C.c_int32), ("schur_tile", C.c_int32 * 5),
-                ("verify_schedule", C.c_int32)]
+                ("verify_schedule", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 class dd_info(C.Structure):
@@ -47,7 +47,7 @@ class dd_info(C.Structure):
                 ("max_front_aux", C.c_int32), ("max_front_domain", C.c_int32), ("refine_iters", C.c_int32),
                 ("rel_resid", C.c_double), ("n_perturbed", C.c_int32), ("numeric_flags", C.c_int32),
                 ("bytes_solve", C.c_double), ("rel_resid_torn", C.c_double), ("bad_domain", C.c_int32),
-                ("n_pivot_2x2", C.c_int32), ("n_interchanges", C.c_int32), ("reserved_", C.c_int32)]
+                ("n_pivot_2x2", C.c_int32), ("n_interchanges", C.c_int32), ("tuned_from_cache", C.c_int32)]
 
 
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
@@ -128,7 +128,7 @@ class Solver:
 
     def __init__(self, rowptr, colind, n_mult, imap_ptr, imap_dof, imap_mult, imap_sign, xyz=None,
                  precision="fp64", max_rhs=64, leaf_size=48, refine_tol=1e-9, refine_maxit=20,
-                 use_graph=False, verbose=False, schur_tile=None, verify_schedule=False):
+                 use_graph=False, verbose=False, schur_tile=None, verify_schedule=False, tune_cache=None):
         lib = load()
         self._lib = lib
         nd = len(rowptr)
@@ -162,6 +162,8 @@ class Solver:
         opt.verbose = int(bool(verbose))
         opt.use_graph = 2 if use_graph == "solve" else int(bool(use_graph))
         opt.verify_schedule = int(bool(verify_schedule))
+        self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
+        opt.tune_cache = self._tune_cache
         if schur_tile is not None:
             assert len(schur_tile) == TILE_BUCKETS
             for b, t in enumerate(schur_tile):
@@ -236,7 +238,14 @@ class Solver:
         vec = f.dim() == 1
         F = f.reshape(self.n_torn, -1)
         nrhs = F.shape[1]
-        fc = F.t().contiguous()                 # column-major, ld = n_torn
+        # column-major staging (ld = n_torn), reused across calls: the
+        # library's graphs of a refined solve are kept per right-hand-side
+        # pointer
+        fb = getattr(self, "_fbuf", None)
+        if fb is None or fb.shape[0] != nrhs or fb.device != F.device:
+            fb = self._fbuf = torch.empty((nrhs, self.n_torn), dtype=torch.complex128, device=F.device)
+        fb.copy_(F.t())
+        fc = fb
         u = torch.empty_like(fc)
         lam = torch.empty((nrhs, self.n_mult), dtype=torch.complex128, device=fc.device) if return_lam else None
         st = self._lib.dd_solve(self._ctx, nrhs, C.c_void_p(fc.data_ptr()), self.n_torn, C.c_void_p(u.data_ptr()),

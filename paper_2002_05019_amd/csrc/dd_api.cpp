@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <tuple>
 #include <utility>
 #include <cmath>
 #include <cstdio>
@@ -59,11 +60,19 @@ struct dd_ctx_s {
   hipStream_t cap = nullptr;
   std::map<const void *, hipGraphExec_t> gfactor;
   std::map<std::pair<int, int>, hipGraphExec_t> gsolve;
+  // refined solve of one column block as one graph, per (columns,
+  // iterations enqueued, right-hand side pointer, its leading dimension)
+  std::map<std::tuple<int, int, const void *, int64_t>, hipGraphExec_t> grefine;
+  // correction iterations the last refined solve needed (the next one
+  // enqueues as many before it synchronises)
+  int refine_guess = 2;
   // look-ahead of the factorisation: side stream and its two events
   dd::SideStream side;
   // device whose static workspace array this context is bound to (-1: a
   // caller-owned workspace)
   int static_dev = -1;
+  std::string tune_cache;      // dd_options.tune_cache (copied)
+  bool tuned_from_cache = false;
 };
 
 namespace {
@@ -77,8 +86,10 @@ bool static_stale(const dd_ctx_s *c) { return c->static_dev >= 0 && g_static_own
 void drop_graphs(dd_ctx_s *c) {
   for (auto &kv : c->gfactor) (void)hipGraphExecDestroy(kv.second);
   for (auto &kv : c->gsolve) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : c->grefine) (void)hipGraphExecDestroy(kv.second);
   c->gfactor.clear();
   c->gsolve.clear();
+  c->grefine.clear();
 }
 
 // Records `enqueue` (launches only) on the capture stream into an executable graph.
@@ -133,6 +144,64 @@ dd_status factor_status(const dd_ctx_s *c) {
   return DD_OK;
 }
 
+// Tile-cache key: the device's architecture and CU count, the precision,
+// and an FNV-1a hash of every front's (kind, n, s) in plan order.
+std::string tune_key(const dd_ctx_s *c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(c->plan.precision);
+  for (const dd::FrontDev &d : c->plan.fronts) {
+    mix(d.kind);
+    mix(d.n);
+    mix(d.s);
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char &ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s/%dcu/p%d/%016llx", arch.c_str(), cus, c->plan.precision, (unsigned long long)h);
+  return buf;
+}
+
+// Tiles of `key` from the cache file (false if absent or malformed).
+bool cache_lookup(const std::string &path, const std::string &key, int *tiles) {
+  FILE *fp = fopen(path.c_str(), "r");
+  if (!fp) return false;
+  char line[512], k[256];
+  bool found = false;
+  while (fgets(line, sizeof line, fp)) {
+    int t[dd::TILE_BUCKETS];
+    if (sscanf(line, "%255s %d %d %d %d %d", k, &t[0], &t[1], &t[2], &t[3], &t[4]) != 6) continue;
+    if (key != k) continue;
+    bool ok = true;
+    for (int b = 0; b < dd::TILE_BUCKETS; ++b) ok = ok && (t[b] == 0 || t[b] == 64 || t[b] == 128);
+    if (!ok) continue;
+    for (int b = 0; b < dd::TILE_BUCKETS; ++b) tiles[b] = t[b];
+    found = true;   // the last matching line wins
+  }
+  fclose(fp);
+  return found;
+}
+
+void cache_append(const std::string &path, const std::string &key, const int *tiles) {
+  FILE *fp = fopen(path.c_str(), "a");
+  if (!fp) return;
+  fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), tiles[0], tiles[1], tiles[2], tiles[3], tiles[4]);
+  fclose(fp);
+}
+
 hipError_t run_solve_core(dd_ctx_s *c, int nrhs, bool with_c, hipStream_t st, bool subset = false) {
   if (!c->opt.use_graph) return dd::solve_core(c->plan, c->ws, nrhs, with_c, st, nullptr, subset);
   auto key = std::make_pair(nrhs, (with_c ? 1 : 0) + (subset ? 2 : 0));
@@ -167,6 +236,7 @@ void dd_default_options(dd_options *o) {
   o->verbose = 0;
   for (int b = 0; b < DD_TILE_BUCKETS; ++b) o->schur_tile[b] = 0;
   o->verify_schedule = 0;
+  o->tune_cache = nullptr;
 }
 
 const char *dd_last_error(void) { return g_err.c_str(); }
@@ -249,6 +319,8 @@ dd_status dd_setup(const dd_problem *prob, const dd_options *opt, dd_ctx *out) {
       }
     }
     if (prob->dof_xyz) c->xyz.assign(prob->dof_xyz, prob->dof_xyz + 3 * ntot);
+    if (o.tune_cache) c->tune_cache = o.tune_cache;
+    o.tune_cache = nullptr;   // the context keeps its own copy
     c->opt = o;
     c->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = c;
@@ -391,9 +463,9 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
     const dd_z *fj = f + (int64_t)j0 * ldf;
     dd_z *uj = u + (int64_t)j0 * ldu;
     dd_z *lj = lam ? lam + (int64_t)j0 * ldl : nullptr;
-    HIPCHECK(dd::rhs_in(P, c->ws, fj, ldf, nb, st));
-    HIPCHECK(run_solve_core(c, nb, false, st));
     if (P.precision == 0) {
+      HIPCHECK(dd::rhs_in(P, c->ws, fj, ldf, nb, st));
+      HIPCHECK(run_solve_core(c, nb, false, st));
       HIPCHECK(dd::sol_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
       continue;
     }
@@ -402,45 +474,68 @@ dd_status dd_solve(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, 
     // [f - K u - B^T lam; -B u], whose FP32 solve gives the correction, and
     // the assembled one, f - A u~ with every DoF taken from its
     // representative copy (the residual of the undecomposed FEM system,
-    // A = sum_i R_i^T K_i R_i).  Stop when both are within refine_tol.
-    const int64_t mr = P.max_rhs;
-    std::vector<double> fn(2 * nb), rn(2 * nb);
-    double *r64 = (double *)(c->ws + P.b_r64);
-    HIPCHECK(dd::refine_init(P, c->ws, nb, st));
-    HIPCHECK(dd::refine_resid(P, c->ws, fj, ldf, nb, true, st));
-    HIPCHECK(hipMemcpyAsync(fn.data(), r64 + P.r_fnorm, nb * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(fn.data() + nb, r64 + P.r_fnorm + mr, nb * 8, hipMemcpyDeviceToHost, st));
-    int it = 0;
-    double rel_t = 0, rel_g = 0;
-    for (;;) {
-      HIPCHECK(dd::refine_resid(P, c->ws, fj, ldf, nb, false, st));
-      HIPCHECK(hipMemcpyAsync(rn.data(), r64 + P.r_norm, nb * 8, hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipMemcpyAsync(rn.data() + nb, r64 + P.r_norm + mr, nb * 8, hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipStreamSynchronize(st));
-      rel_t = rel_g = 0;
-      bool bad = false;
-      for (int j = 0; j < nb; ++j) {
-        const double rt = fn[j] > 0 ? std::sqrt(rn[j] / fn[j]) : std::sqrt(rn[j]);
-        const double rg = fn[nb + j] > 0 ? std::sqrt(rn[nb + j] / fn[nb + j]) : std::sqrt(rn[nb + j]);
-        if (!std::isfinite(rt) || !std::isfinite(rg)) bad = true;
-        rel_t = std::max(rel_t, rt);
-        rel_g = std::max(rel_g, rg);
+    // A = sum_i R_i^T K_i R_i).  Converged when both are within refine_tol.
+    // The test runs on the device: the first solve, the residuals and K
+    // correction iterations (as many as the last refined solve needed) are
+    // enqueued at once, or replayed as one graph, and the iterations after
+    // convergence return at once; the host synchronises once and continues
+    // one iteration at a time only if K were not enough.
+    const double tol = c->opt.refine_tol;
+    const int *gate = dd::refine_ctl(P, c->ws);
+    auto iteration = [&](hipStream_t s) -> hipError_t {
+      hipError_t e = dd::solve_core(P, c->ws, nb, true, s, nullptr, false, gate);
+      if (e == hipSuccess) e = dd::refine_update(P, c->ws, nb, s, gate);
+      if (e == hipSuccess) e = dd::refine_resid(P, c->ws, fj, ldf, nb, false, s, gate);
+      if (e == hipSuccess) e = dd::refine_test(P, c->ws, nb, tol, true, s);
+      return e;
+    };
+    const int K = std::min(c->opt.refine_maxit, std::max(0, c->refine_guess));
+    auto sequence = [&](hipStream_t s) -> hipError_t {
+      hipError_t e = dd::rhs_in(P, c->ws, fj, ldf, nb, s);
+      if (e == hipSuccess) e = dd::solve_core(P, c->ws, nb, false, s);
+      if (e == hipSuccess) e = dd::refine_ctl_reset(P, c->ws, s);
+      if (e == hipSuccess) e = dd::refine_init(P, c->ws, nb, s);
+      if (e == hipSuccess) e = dd::refine_resid(P, c->ws, fj, ldf, nb, true, s);
+      if (e == hipSuccess) e = dd::refine_resid(P, c->ws, fj, ldf, nb, false, s);
+      if (e == hipSuccess) e = dd::refine_test(P, c->ws, nb, tol, false, s);
+      for (int k = 0; k < K && e == hipSuccess; ++k) e = iteration(s);
+      return e;
+    };
+    if (c->opt.use_graph) {
+      const auto key = std::make_tuple(nb, K, (const void *)fj, ldf);
+      auto itg = c->grefine.find(key);
+      if (itg == c->grefine.end()) {
+        hipGraphExec_t ge;
+        HIPCHECK(capture(c, sequence, &ge));
+        itg = c->grefine.emplace(key, ge).first;
       }
-      if (bad) {
-        result = DD_ERR_NUMERIC;
-        g_err = "non-finite residual during refinement";
-        break;
-      }
-      if (std::max(rel_t, rel_g) <= c->opt.refine_tol) break;
-      if (it >= c->opt.refine_maxit) {
-        // perturbed pivots are the likely cause: report them
-        result = fst != DD_OK ? fst : DD_ERR_NOT_CONVERGED;
-        if (fst == DD_OK) g_err = "refinement did not reach refine_tol";
-        break;
-      }
-      HIPCHECK(run_solve_core(c, nb, true, st));
-      HIPCHECK(dd::refine_update(P, c->ws, nb, st));
-      ++it;
+      HIPCHECK(hipGraphLaunch(itg->second, st));
+    } else {
+      HIPCHECK(sequence(st));
+    }
+    int ctl[3];
+    double relv[2];
+    auto fetch = [&]() -> hipError_t {
+      hipError_t e = hipMemcpyAsync(ctl, gate, sizeof ctl, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(relv, dd::refine_rel(P, c->ws), sizeof relv, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      return e;
+    };
+    HIPCHECK(fetch());
+    while (!ctl[0] && ctl[1] < c->opt.refine_maxit) {
+      HIPCHECK(iteration(st));
+      HIPCHECK(fetch());
+    }
+    const int it = ctl[1];
+    const double rel_t = relv[0], rel_g = relv[1];
+    c->refine_guess = it;
+    if (ctl[2]) {
+      result = DD_ERR_NUMERIC;
+      g_err = "non-finite residual during refinement";
+    } else if (!ctl[0]) {
+      // perturbed pivots are the likely cause: report them
+      result = fst != DD_OK ? fst : DD_ERR_NOT_CONVERGED;
+      if (fst == DD_OK) g_err = "refinement did not reach refine_tol";
     }
     HIPCHECK(dd::refine_out(P, c->ws, uj, ldu, lj, ldl, nb, st));
     c->refine_iters = std::max(c->refine_iters, it);
@@ -518,6 +613,7 @@ dd_status dd_get_info(dd_ctx c, dd_info *info) {
   info->rel_resid = c->rel_resid;
   info->rel_resid_torn = c->rel_resid_torn;
   info->bad_domain = -1;
+  info->tuned_from_cache = c->tuned_from_cache ? 1 : 0;
   if (c->events) {
     float ms = 0;
     if (c->fact_rec) {
@@ -610,11 +706,13 @@ dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
   }
   try {
     hipStream_t st = (hipStream_t)stream;
+    int choice[dd::TILE_BUCKETS];
+    const std::string key = tune_key(c);
+    c->tuned_from_cache = !c->tune_cache.empty() && cache_lookup(c->tune_cache, key, choice);
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
-    int choice[dd::TILE_BUCKETS];
-    for (int b = 0; b < dd::TILE_BUCKETS; ++b) {
+    for (int b = 0; b < dd::TILE_BUCKETS && !c->tuned_from_cache; ++b) {
       choice[b] = 0;
       const dd::Launch &l64 = c->plan.tune[b][0], &l128 = c->plan.tune[b][1];
       if (l64.count == 0 || l128.count == 0) continue;
@@ -635,6 +733,7 @@ dd_status dd_tune(dd_ctx c, int32_t *schur_tile, void *stream) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (!c->tune_cache.empty() && !c->tuned_from_cache) cache_append(c->tune_cache, key, choice);
     // re-plan with the chosen policy (same workspace layout) and upload
     dd::SetupOptions so = c->so;
     for (int b = 0; b < dd::TILE_BUCKETS; ++b) {

@@ -20,7 +20,7 @@ hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nr
 // subset: the backward substitution skips the domains whose byte in the
 // workspace's domain mask is 0)
 hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm = nullptr,
-                      bool subset = false);
+                      bool subset = false, const int *gate = nullptr);
 // internal solution / multipliers -> interleaved complex FP64 (subset: only
 // the rows of the domains selected in the domain mask)
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
@@ -31,9 +31,19 @@ hipError_t interface_inverse_out(const Plan &P, uint8_t *ws, int front, void *ou
 // SELL-64 layout, read by the refinement residual
 hipError_t operator_copy(const Plan &P, uint8_t *ws, const void *vals, hipStream_t st);
 hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st);
-hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st);
+// gate (device int, may be null): the launches return at once while it is
+// nonzero (a converged refinement skips its remaining enqueued iterations)
+hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st, const int *gate = nullptr);
 hipError_t refine_resid(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, bool fnorm,
-                        hipStream_t st);
+                        hipStream_t st, const int *gate = nullptr);
+// refinement control words in the workspace: [0] converged (or non-finite),
+// [1] correction iterations that ran, [2] non-finite residual; and the last
+// maxima of the torn and the assembled relative residual (2 doubles)
+int *refine_ctl(const Plan &P, uint8_t *ws);
+const double *refine_rel(const Plan &P, uint8_t *ws);
+hipError_t refine_ctl_reset(const Plan &P, uint8_t *ws, hipStream_t st);
+// convergence test of the last residual (count: a correction preceded it)
+hipError_t refine_test(const Plan &P, uint8_t *ws, int nrhs, double tol, bool count, hipStream_t st);
 hipError_t refine_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
                       hipStream_t st);
 

@@ -57,6 +57,9 @@ struct KP {
   const int32_t *grep;
   const int32_t *gcp;
   const int32_t *gcr;
+  // refinement control: the kernels of a correction iteration return at
+  // once when *skip is nonzero (the refinement has converged); null: ungated
+  const int *skip;
   int64_t n_gcomp;
   int64_t rg;      // offset (doubles) of the assembled-residual rows in r64
   T *num;
@@ -1295,6 +1298,11 @@ template <typename T>
 __device__ __forceinline__ bool skipped(const KP<T> &p, const FrontDev &f) {
   return p.dmask && f.dom >= 0 && !p.dmask[f.dom];
 }
+// a converged refinement skips the rest of its enqueued iterations
+template <typename T>
+__device__ __forceinline__ bool gated(const KP<T> &p) {
+  return p.skip && *(volatile const int *)p.skip != 0;
+}
 
 // ---------------------------------------------------------------------------
 // multi-RHS substitutions (front vectors v: n x mr planar, ld n)
@@ -1302,6 +1310,7 @@ __device__ __forceinline__ bool skipped(const KP<T> &p, const FrontDev &f) {
 // fully-summed rows plus the children's update parts (extend-add).
 template <typename T>
 __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int n = f.n, s = f.s, r = it.i + threadIdx.x;
@@ -1375,6 +1384,7 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
 // applied by the thread of its first row).
 template <typename T>
 __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int n = f.n, a = it.i + threadIdx.x;
@@ -1419,6 +1429,7 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
 // solution vector.
 template <typename T>
 __global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   if (skipped(p, f)) return;
@@ -1453,6 +1464,7 @@ __global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs)
 // solution vector.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   if (skipped(p, f)) return;
@@ -1685,6 +1697,7 @@ __device__ __forceinline__ void apply_dinv(const KP<T> &p, const FrontDev &f, T 
 // v(rows below) -= L21 y_k, finally z = D^-1 y.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ffront(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   __shared__ T sr[NB][65], si[NB][65];
   __shared__ T yr[NB][NB + 1], yi[NB][NB + 1];
   const Item it = p.items[first + blockIdx.x];
@@ -1740,6 +1753,7 @@ __global__ __launch_bounds__(256) void k_ffront(KP<T> p, int64_t first, int nrhs
 // (z_k - L21^T x_below), finally the fully-summed part is scattered.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bfront(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   if (skipped(p, p.F[p.items[first + blockIdx.x].f])) return;
   __shared__ T lr[64][NB + 1], li[64][NB + 1];
   __shared__ T xr[64][17], xi[64][17];
@@ -1865,6 +1879,7 @@ __device__ __forceinline__ void zq_out(T *ps, const typename V4<T>::t &P, const 
 // M = 0, 1 (A(o, k) a row block of the front, contiguous along o)
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zq_n(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   __shared__ __align__(16) T xs[ZKC * 16];
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -1927,6 +1942,7 @@ __global__ __launch_bounds__(256) void k_zq_n(KP<T> p, int64_t first, int nrhs) 
 // the front staged in LDS with coalesced loads
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zq_t(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   __shared__ T at[2][64][65];
   __shared__ __align__(16) T xs[64 * 16];
   const Item it = p.items[first + blockIdx.x];
@@ -2011,6 +2027,7 @@ __device__ __forceinline__ void zslot_out(const typename V4<T>::t (&cr)[2][2], c
 // three waves per SIMD (no spills at that register budget)
 template <typename T, int M>
 __global__ __launch_bounds__(256, 3) void k_zmma_n(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -2054,6 +2071,7 @@ __global__ __launch_bounds__(256, 3) void k_zmma_n(KP<T> p, int64_t first, int n
 // M = 2, 3: A(o, k) is a column block of the front read along its rows k
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -2095,6 +2113,7 @@ __global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs
 // Reduction of the partial slots [it.k, it.k + it.j) of output tile it.i.
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) {
+  if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   if (M >= 2 && skipped(p, f)) return;   // backward reductions only
@@ -2135,6 +2154,7 @@ __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) 
 // blocks of the right-hand sides over the full inner dimension g
 template <typename T>
 __global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
+  if (gated(p)) return;
   if (mode == 1 && skipped(p, p.F[p.gemv[blockIdx.x].f])) return;
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.gemv[blockIdx.x];
@@ -2191,6 +2211,7 @@ __global__ __launch_bounds__(256) void k_xmma(KP<T> p, int mode, int nrhs) {
 // 256 columns of X at a time
 template <typename T>
 __global__ __launch_bounds__(256) void k_xq(KP<T> p, int mode, int nrhs) {
+  if (gated(p)) return;
   if (mode == 1 && skipped(p, p.F[p.gemv[blockIdx.x].f])) return;
   __shared__ __align__(16) T xs[256 * 16];
   const Item it = p.gemv[blockIdx.x];
@@ -2256,6 +2277,7 @@ __global__ __launch_bounds__(256) void k_xq(KP<T> p, int mode, int nrhs) {
 // d(p) = sum_t s_t YG_t - c(p)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mgather(KP<T> p, int nrhs, int with_c) {
+  if (gated(p)) return;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= p.n_mult * nrhs) return;
   const int64_t m = e % p.n_mult, j = e / p.n_mult;
@@ -2283,6 +2305,7 @@ __global__ __launch_bounds__(256) void k_mgather(KP<T> p, int nrhs, int with_c) 
 // h(gamma) = sum over multipliers on that dof of sign * lambda
 template <typename T>
 __global__ __launch_bounds__(256) void k_hgather(KP<T> p, int64_t ngam, int nrhs) {
+  if (gated(p)) return;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= ngam * nrhs) return;
   const int64_t q = e % ngam, j = e / ngam;
@@ -2369,6 +2392,7 @@ __global__ void k_r_init(KP<T> p, int nrhs) {
 
 template <typename T>
 __global__ void k_r_update(KP<T> p, int nrhs) {
+  if (gated(p)) return;
   const int64_t mr = p.mr;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t nt = p.n_torn * nrhs, nm = p.n_mult * nrhs;
@@ -2405,6 +2429,7 @@ __global__ __launch_bounds__(256) void k_sell_fill(const int64_t *csrp, const in
 template <typename T>
 __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t ldf, int nrhs, int64_t part_off,
                                                  int fnorm) {
+  if (gated(p)) return;
   __shared__ double red[8][256];
   const int64_t mr = p.mr;
   const double *U = p.r64;
@@ -2529,6 +2554,7 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
 // rows of f - K u~, squared and summed per column into per-block partials.
 template <typename T>
 __global__ __launch_bounds__(256) void k_r_gsum(KP<T> p, int nrhs, int64_t part_off) {
+  if (gated(p)) return;
   __shared__ double red[8][256];
   const int64_t mr = p.mr, nt = p.n_torn;
   const double *G = p.r64 + p.rg;
@@ -2570,9 +2596,9 @@ __global__ __launch_bounds__(256) void k_r_gsum(KP<T> p, int nrhs, int64_t part_
   }
 }
 
-__global__ void k_r_reduce(const double *part, int nblk, int nrhs, double *out) {
+__global__ void k_r_reduce(const double *part, int nblk, int nrhs, double *out, const int *skip) {
   const int j = blockIdx.x;
-  if (j >= nrhs) return;
+  if (j >= nrhs || (skip && *(volatile const int *)skip)) return;
   __shared__ double red[256];
   double a = 0;
   for (int b = threadIdx.x; b < nblk; b += 256) a += part[b + (int64_t)j * nblk];
@@ -2583,6 +2609,51 @@ __global__ void k_r_reduce(const double *part, int nblk, int nrhs, double *out) 
     __syncthreads();
   }
   if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// Convergence test of the refinement (one workgroup).  Per column the torn
+// and the assembled squared residual norms relative to the right-hand
+// side's; ctl[0] is set when every column has both within tol (or a value is
+// not finite: ctl[2]), ctl[1] counts the correction iterations that ran
+// (count = 1 after a correction), rel receives the two maxima.  A test of an
+// iteration that was skipped (ctl[0] already set) does nothing.
+__global__ __launch_bounds__(256) void k_r_test(const double *norm, const double *fnorm, int nrhs, int mr, double tol,
+                                                int *ctl, double *rel, int count) {
+  if (*(volatile int *)ctl) return;
+  __shared__ double mt[256], mg[256];
+  __shared__ int bad[256];
+  double rt = 0, rg = 0;
+  int b = 0;
+  for (int j = threadIdx.x; j < nrhs; j += 256) {
+    const double t = fnorm[j] > 0 ? sqrt(norm[j] / fnorm[j]) : sqrt(norm[j]);
+    const double g = fnorm[mr + j] > 0 ? sqrt(norm[mr + j] / fnorm[mr + j]) : sqrt(norm[mr + j]);
+    if (!isfinite(t) || !isfinite(g)) b = 1;
+    rt = fmax(rt, t);
+    rg = fmax(rg, g);
+  }
+  mt[threadIdx.x] = rt;
+  mg[threadIdx.x] = rg;
+  bad[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      mt[threadIdx.x] = fmax(mt[threadIdx.x], mt[threadIdx.x + st]);
+      mg[threadIdx.x] = fmax(mg[threadIdx.x], mg[threadIdx.x + st]);
+      bad[threadIdx.x] |= bad[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctl[1] += count;
+    rel[0] = mt[0];
+    rel[1] = mg[0];
+    if (bad[0]) ctl[2] = 1;
+    if (bad[0] || fmax(mt[0], mg[0]) <= tol) ctl[0] = 1;
+  }
+}
+
+__global__ void k_r_ctl_reset(int *ctl) {
+  if (threadIdx.x < 4) ctl[threadIdx.x] = 0;
 }
 
 template <typename T>
@@ -2633,6 +2704,7 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
   k.gcr = (const int32_t *)(m + P.m_gcr);
   k.n_gcomp = P.n_gcomp;
   k.rg = P.r_g;
+  k.skip = nullptr;
   k.num = (T *)(ws + P.b_num);
   uint8_t *sd = ws + P.b_side;
   k.dinv = (cd *)sd;
@@ -2746,9 +2818,10 @@ static hipError_t factor_t(const Plan &P, uint8_t *ws, const void *vals, hipStre
 
 template <typename T>
 static hipError_t solve_core_t(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm,
-                               bool subset) {
+                               bool subset, const int *gate) {
   KP<T> k = make_kp<T>(P, ws, nullptr);
   if (subset) k.dmask = ws + P.b_dmask;
+  k.skip = gate;
   hipError_t e = run_seq<T>(P, k, P.solve_dom_fwd, nrhs, st, tm);
   if (e != hipSuccess) return e;
   if (!P.gemv_items.empty())
@@ -2789,9 +2862,10 @@ hipError_t rhs_in(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nr
   return hipGetLastError();
 }
 
-hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm, bool subset) {
-  return P.precision == 0 ? solve_core_t<double>(P, ws, nrhs, with_c, st, tm, subset)
-                          : solve_core_t<float>(P, ws, nrhs, with_c, st, tm, subset);
+hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStream_t st, KTimer *tm, bool subset,
+                      const int *gate) {
+  return P.precision == 0 ? solve_core_t<double>(P, ws, nrhs, with_c, st, tm, subset, gate)
+                          : solve_core_t<float>(P, ws, nrhs, with_c, st, tm, subset, gate);
 }
 
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
@@ -2836,23 +2910,37 @@ hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_r_init<float>, dim3(nblk((P.n_torn + P.n_mult) * nrhs)), dim3(256), 0, st, k, nrhs);
   return hipGetLastError();
 }
-hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st) {
+hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st, const int *gate) {
   KP<float> k = make_kp<float>(P, ws, ws + P.b_vals);
+  k.skip = gate;
   hipLaunchKernelGGL(k_r_update<float>, dim3(nblk((P.n_torn + P.n_mult) * nrhs)), dim3(256), 0, st, k, nrhs);
   return hipGetLastError();
 }
 hipError_t refine_resid(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, bool fnorm,
-                        hipStream_t st) {
+                        hipStream_t st, const int *gate) {
   KP<float> k = make_kp<float>(P, ws, ws + P.b_vals);
+  k.skip = gate;
   const int nb = (int)P.r_nblk;
   hipLaunchKernelGGL(k_r_resid<float>, dim3(nb), dim3(256), 0, st, k, (const cd *)f, ldf, nrhs, P.r_part,
                      fnorm ? 1 : 0);
   double *r64 = (double *)(ws + P.b_r64);
   double *out = r64 + (fnorm ? P.r_fnorm : P.r_norm);
-  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + P.r_part, nb, nrhs, out);
+  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + P.r_part, nb, nrhs, out, gate);
   const int64_t gpart = P.r_part + P.r_nblk * P.max_rhs;
   hipLaunchKernelGGL(k_r_gsum<float>, dim3(nb), dim3(256), 0, st, k, nrhs, gpart);
-  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + gpart, nb, nrhs, out + P.max_rhs);
+  hipLaunchKernelGGL(k_r_reduce, dim3(nrhs), dim3(256), 0, st, r64 + gpart, nb, nrhs, out + P.max_rhs, gate);
+  return hipGetLastError();
+}
+int *refine_ctl(const Plan &P, uint8_t *ws) { return (int *)(ws + P.b_status) + 16; }
+const double *refine_rel(const Plan &P, uint8_t *ws) { return (const double *)(ws + P.b_r64) + P.r_ctl; }
+hipError_t refine_ctl_reset(const Plan &P, uint8_t *ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_r_ctl_reset, dim3(1), dim3(64), 0, st, refine_ctl(P, ws));
+  return hipGetLastError();
+}
+hipError_t refine_test(const Plan &P, uint8_t *ws, int nrhs, double tol, bool count, hipStream_t st) {
+  double *r64 = (double *)(ws + P.b_r64);
+  hipLaunchKernelGGL(k_r_test, dim3(1), dim3(256), 0, st, r64 + P.r_norm, r64 + P.r_fnorm, nrhs, (int)P.max_rhs, tol,
+                     refine_ctl(P, ws), r64 + P.r_ctl, count ? 1 : 0);
   return hipGetLastError();
 }
 hipError_t refine_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,

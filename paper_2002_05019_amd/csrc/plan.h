@@ -152,7 +152,7 @@ struct Plan {
   std::vector<uint8_t> meta;           // serialised meta blob
   // FP64 refinement vectors (doubles, planar) inside the r64 region
   // r_g: per torn row f - K u~ with u~ the representative copies (FP64 planar)
-  int64_t r_u = 0, r_l = 0, r_g = 0, r_norm = 0, r_fnorm = 0, r_part = 0;
+  int64_t r_u = 0, r_l = 0, r_g = 0, r_norm = 0, r_fnorm = 0, r_part = 0, r_ctl = 0;
   int64_t r_nblk = 0;
 
   // ---- statistics

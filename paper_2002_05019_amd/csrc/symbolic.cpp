@@ -1485,6 +1485,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     P.r_part = r; r += 2 * P.r_nblk * mr;
     P.r_norm = r; r += 2 * mr;    // squared norms: torn [0, mr), global [mr, 2 mr)
     P.r_fnorm = r; r += 2 * mr;
+    P.r_ctl = r; r += 4;          // last torn / assembled residual maxima
     b = A256(b + r * 8);
   }
   P.b_status = b; b = A256(b + 256);

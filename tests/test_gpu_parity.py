@@ -201,3 +201,57 @@ def test_many_rhs_on_matrix_cores(precision):
     assert _colerr(u.cpu().numpy(), ref["u"]) < tol
     if precision == "fp32_refine":
         assert s.info()["rel_resid"] <= 1e-9
+
+
+def test_tune_cache(tmp_path):
+    """The tile tuner's cache: the first context measures and appends its
+    line, a second context of the same problem takes the tiles from the
+    file, and its factorisation matches the oracle."""
+    from paper_2002_05019_amd.binding import Solver
+    c = cached_case("cube18u")
+    path = tmp_path / "tiles.txt"
+    print("[parity] tune cache cube18u", flush=True)
+    s1 = Solver.from_case(c, tune_cache=path).bind(DEV)
+    t1 = s1.tune()
+    assert s1.info()["tuned_from_cache"] == 0
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:] == [str(t) for t in t1]
+    s2 = Solver.from_case(c, tune_cache=path).bind(DEV)
+    t2 = s2.tune()
+    assert s2.info()["tuned_from_cache"] == 1 and t2 == t1
+    assert len(path.read_text().splitlines()) == 1
+    s2.factor(torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV))
+    u = s2.solve(_rhs(c))
+    assert _colerr(u.cpu().numpy(), _ref("cube18u")["u"]) < 1e-10
+    # another shape (FP32 fronts) gets a line of its own
+    s3 = Solver.from_case(c, precision="fp32_refine", tune_cache=path).bind(DEV)
+    s3.tune()
+    assert s3.info()["tuned_from_cache"] == 0 and len(path.read_text().splitlines()) == 2
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_refinement_cap_and_device_control(graph):
+    """Refinement control on the device: with a cap of one correction the
+    solve reports DD_ERR_NOT_CONVERGED (u still written, one iteration
+    counted); with the default cap the same context converges, and a repeat
+    solve (which enqueues as many corrections as the last one needed)
+    returns the same bits."""
+    from paper_2002_05019_amd.binding import Solver
+    c = cached_case("cube16")
+    vals = torch.from_numpy(np.concatenate([d.K.data for d in c.domains])).to(DEV)
+    print(f"[parity] refinement cap cube16 graph={graph}", flush=True)
+    s = Solver.from_case(c, precision="fp32_refine", refine_maxit=1, use_graph=graph).bind(DEV)
+    s.factor(vals)
+    u1 = s.solve(_rhs(c), check=False).cpu().numpy()
+    info = s.info()
+    assert s.last_status == -8 and info["refine_iters"] == 1
+    assert 1e-9 < info["rel_resid"] < 1e-3
+    assert np.isfinite(u1).all()
+    m = Solver.from_case(c, precision="fp32_refine", use_graph=graph).bind(DEV)
+    m.factor(vals)
+    ua = m.solve(_rhs(c)).cpu().numpy()
+    it = m.info()["refine_iters"]
+    ub = m.solve(_rhs(c)).cpu().numpy()
+    assert m.last_status == 0 and m.info()["refine_iters"] == it >= 1
+    assert np.array_equal(ua, ub)
+    assert oracle.global_residual(c, ub).max() <= 1e-9
