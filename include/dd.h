@@ -261,6 +261,19 @@ dd_status dd_solve(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u
 dd_status dd_solve_subset(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, dd_z *u, int64_t ldu,
                           const uint8_t *domain_mask, void *hip_stream);
 
+/* Recovery of selected primal unknowns only (section II: all or a subset of
+ * the primal unknowns are recovered; here at the granularity of single DoFs,
+ * e.g. observation points).  rows: host array of nsel torn row ids (the
+ * torn layout of dd_solve: rows of domain i start at sum_{j<i} n_j); only
+ * the domains holding them are back-substituted, and out (device, nsel x
+ * nrhs column-major, leading dimension ldo >= nsel) receives u at those
+ * rows, equal bit for bit to dd_solve's.  f as in dd_solve.  Synchronises
+ * hip_stream before returning.  FP64 contexts only.
+ * Errors: DD_ERR_ARG (bad row, sizes, FP32_REFINE), DD_ERR_STATE,
+ * DD_ERR_DEVICE. */
+dd_status dd_solve_dofs(dd_ctx ctx, int32_t nrhs, const dd_z *f, int64_t ldf, int64_t nsel, const int64_t *rows,
+                        dd_z *out, int64_t ldo, void *hip_stream);
+
 /* Statistics; synchronises the streams of the last factor/solve. */
 dd_status dd_get_info(dd_ctx ctx, dd_info *info);
 

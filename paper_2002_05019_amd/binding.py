@@ -53,7 +53,7 @@ class dd_info(C.Structure):
 EXPORTS = ["dd_default_options", "dd_setup", "dd_workspace_size", "dd_bind_workspace", "dd_factor",
            "dd_solve", "dd_get_info", "dd_get_interface_dofs", "dd_get_interface_inverse",
            "dd_get_domain_flops", "dd_kernel_timer_start", "dd_kernel_timer_read", "dd_tune", "dd_solve_subset",
-           "dd_bind_static_workspace", "dd_destroy", "dd_last_error"]
+           "dd_bind_static_workspace", "dd_solve_dofs", "dd_destroy", "dd_last_error"]
 STATIC_WORKSPACE_BYTES = 128 << 20   # DD_STATIC_WORKSPACE_BYTES
 TILE_BUCKETS = 5   # front sizes [0,512) [512,1024) [1024,2048) [2048,4096) [4096,...)
 KERNELS = {"schur_update": 0, "panel_solve": 1, "pivot_tile": 2, "inverse_update": 3, "column_update": 4}
@@ -85,6 +85,7 @@ def load():
     lib.dd_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp, C.c_int64, vp]
     lib.dd_solve_subset.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, _P(C.c_uint8), vp]
     lib.dd_get_info.argtypes = [vp, _P(dd_info)]
+    lib.dd_solve_dofs.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int64, _P(C.c_int64), vp, C.c_int64, vp]
     lib.dd_get_interface_dofs.argtypes = [vp, C.c_int32, _P(C.c_int32), _P(C.c_int32)]
     lib.dd_get_interface_inverse.argtypes = [vp, C.c_int32, vp, vp]
     lib.dd_get_domain_flops.argtypes = [vp, C.c_int32, _P(C.c_double)]
@@ -282,6 +283,23 @@ class Solver:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         out = uc.t()
         return out.reshape(-1) if f.dim() == 1 else out
+
+    def solve_dofs(self, f, rows, stream=None, check=True):
+        """Recovers the primal unknowns at the given torn rows only (FP64
+        contexts): returns a (len(rows), nrhs) complex128 device tensor."""
+        import torch
+        F = f.reshape(self.n_torn, -1)
+        nrhs = F.shape[1]
+        fc = F.t().contiguous()
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        out = torch.empty((nrhs, len(r)), dtype=torch.complex128, device=fc.device)
+        st = self._lib.dd_solve_dofs(self._ctx, nrhs, C.c_void_p(fc.data_ptr()), self.n_torn, len(r),
+                                     _ptr(r, C.c_int64), C.c_void_p(out.data_ptr()), max(len(r), 1),
+                                     self._stream(stream))
+        self.last_status = st
+        if check:
+            _check(st)
+        return out.t()
 
     def info(self):
         inf = dd_info()

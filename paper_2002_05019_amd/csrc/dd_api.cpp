@@ -595,6 +595,59 @@ dd_status dd_solve_subset(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, dd
   return DD_OK;
 }
 
+dd_status dd_solve_dofs(dd_ctx c, int32_t nrhs, const dd_z *f, int64_t ldf, int64_t nsel, const int64_t *rows,
+                        dd_z *out, int64_t ldo, void *stream) {
+  if (!c) return fail(DD_ERR_ARG, "null context");
+  const dd::Plan &P = c->plan;
+  if (P.precision != 0)
+    return fail(DD_ERR_ARG, "subset recovery needs the FP64 path (refinement uses every domain's solution)");
+  if (nrhs < 0 || nsel < 0) return fail(DD_ERR_ARG, "negative size");
+  if (nsel > 0 && !rows) return fail(DD_ERR_ARG, "rows is null");
+  if (static_stale(c)) return fail(DD_ERR_STATE, "the static workspace array was bound to another context");
+  if (!c->factored) return fail(DD_ERR_STATE, "dd_solve_dofs before dd_factor");
+  if (nrhs == 0 || nsel == 0) return DD_OK;
+  if (!f || !out) return fail(DD_ERR_ARG, "f or out is null");
+  if (ldf < P.n_torn) return fail(DD_ERR_ARG, "ldf below the torn size");
+  if (ldo < nsel) return fail(DD_ERR_ARG, "ldo below the number of selected rows");
+  if (nsel > P.n_torn) return fail(DD_ERR_ARG, "more selected rows than torn rows");
+  try {
+    std::vector<uint8_t> mask(P.n_dom, 0);
+    for (int64_t i = 0; i < nsel; ++i) {
+      if (rows[i] < 0 || rows[i] >= P.n_torn) return fail(DD_ERR_ARG, "selected row out of range");
+      const int d = (int)(std::upper_bound(P.dom_row.begin(), P.dom_row.end(), rows[i]) - P.dom_row.begin()) - 1;
+      mask[d] = 1;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(read_status(c));
+    const dd_status fst = factor_status(c);
+    if (fst == DD_ERR_NUMERIC) return fst;
+    c->last = st;
+    HIPCHECK(hipMemcpyAsync(c->ws + P.b_dmask, mask.data(), (size_t)P.n_dom, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(c->ws + P.b_sel, rows, (size_t)nsel * 8, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipEventRecord(c->ev[2], st));
+    c->refine_iters = 0;
+    c->rel_resid = 0;
+    for (int32_t j0 = 0; j0 < nrhs; j0 += P.max_rhs) {
+      const int nb = std::min<int32_t>(P.max_rhs, nrhs - j0);
+      HIPCHECK(dd::rhs_in(P, c->ws, f + (int64_t)j0 * ldf, ldf, nb, st));
+      HIPCHECK(run_solve_core(c, nb, false, st, true));
+      HIPCHECK(dd::sel_out(P, c->ws, nsel, out + (int64_t)j0 * ldo, ldo, nb, st));
+    }
+    HIPCHECK(hipEventRecord(c->ev[3], st));
+    // the host arrays were staged by the copies above; wait for them before
+    // returning (the caller may free them)
+    HIPCHECK(hipStreamSynchronize(st));
+    c->solve_rec = true;
+    if (fst != DD_OK) {
+      factor_status(c);
+      return fst;
+    }
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "host allocation failed");
+  }
+  return DD_OK;
+}
+
 dd_status dd_get_info(dd_ctx c, dd_info *info) {
   if (!c || !info) return fail(DD_ERR_ARG, "null argument");
   std::memset(info, 0, sizeof *info);

@@ -26,6 +26,9 @@ hipError_t solve_core(const Plan &P, uint8_t *ws, int nrhs, bool with_c, hipStre
 hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
                    hipStream_t st, bool subset = false);
 hipError_t interface_inverse_out(const Plan &P, uint8_t *ws, int front, void *out, hipStream_t st);
+// the rows listed in the workspace's selection region (nsel torn row ids) of
+// the internal solution -> interleaved complex FP64 out (nsel x nrhs, ld ldo)
+hipError_t sel_out(const Plan &P, uint8_t *ws, int64_t nsel, void *out, int64_t ldo, int nrhs, hipStream_t st);
 // FP64 iterative refinement around the FP32 factorisation
 // FP64 copy of the operator values (caller's CSR order) into the workspace's
 // SELL-64 layout, read by the refinement residual

@@ -2359,6 +2359,16 @@ __global__ void k_t2u(KP<T> p, cd *u, int64_t ldu, int nrhs, int which) {
   u[r + j * ldu] = cd{(double)s[r + j * rows], (double)s[r + j * rows + rows * p.mr]};
 }
 
+// Selected rows of the internal solution: out(i, j) = x(rows[i], j).
+template <typename T>
+__global__ void k_sel_out(KP<T> p, const int64_t *rows, int64_t nsel, cd *out, int64_t ldo, int nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nsel * nrhs) return;
+  const int64_t i = e % nsel, j = e / nsel, r = rows[i];
+  const T *s = p.num + p.vx;
+  out[i + j * ldo] = cd{(double)s[r + j * p.n_torn], (double)s[r + j * p.n_torn + p.n_torn * p.mr]};
+}
+
 template <typename T>
 __global__ void k_xinv_out(KP<T> p, int f_id, cd *out) {
   const FrontDev f = p.F[f_id];
@@ -2882,6 +2892,18 @@ hipError_t sol_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, 
     if (lam && P.n_mult)
       hipLaunchKernelGGL(k_t2u<float>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, (cd *)lam, ldl, nrhs, 1);
   }
+  return hipGetLastError();
+}
+
+hipError_t sel_out(const Plan &P, uint8_t *ws, int64_t nsel, void *out, int64_t ldo, int nrhs, hipStream_t st) {
+  if (nsel == 0) return hipSuccess;
+  const int64_t *rows = (const int64_t *)(ws + P.b_sel);
+  if (P.precision == 0)
+    hipLaunchKernelGGL(k_sel_out<double>, dim3(nblk(nsel * nrhs)), dim3(256), 0, st, make_kp<double>(P, ws, nullptr),
+                       rows, nsel, (cd *)out, ldo, nrhs);
+  else
+    hipLaunchKernelGGL(k_sel_out<float>, dim3(nblk(nsel * nrhs)), dim3(256), 0, st, make_kp<float>(P, ws, nullptr),
+                       rows, nsel, (cd *)out, ldo, nrhs);
   return hipGetLastError();
 }
 

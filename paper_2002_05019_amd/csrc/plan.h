@@ -144,7 +144,8 @@ struct Plan {
   int64_t vf_off = 0, vx_off = 0, vd_off = 0, vl_off = 0, vc_off = 0, part_off = 0;
   int64_t side_n = 0;                  // fully-summed positions (side arrays)
   // byte offsets inside the workspace
-  int64_t b_meta = 0, b_num = 0, b_side = 0, b_vals = 0, b_r64 = 0, b_status = 0, b_dmask = 0, b_total = 0;
+  int64_t b_meta = 0, b_num = 0, b_side = 0, b_vals = 0, b_r64 = 0, b_status = 0, b_dmask = 0, b_sel = 0,
+          b_total = 0;
   // offsets (bytes) of each meta array inside the meta blob
   int64_t m_fronts, m_vars, m_cfront, m_crmap, m_rmap, m_spairs, m_aux, m_gpos, m_gsign,
       m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_sellp, m_sellc, m_domrow,

@@ -1490,6 +1490,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   }
   P.b_status = b; b = A256(b + 256);
   P.b_dmask = b; b = A256(b + std::max(1, p.n_dom));   // domain mask of the subset solve
+  P.b_sel = b; b = A256(b + 8 * std::max<int64_t>(1, P.n_torn));   // selected rows (dd_solve_dofs)
   P.b_total = b;
 
   if (o.verbose) {

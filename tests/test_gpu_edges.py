@@ -156,6 +156,25 @@ def test_subset_recovery_against_oracle():
         assert _colerr(u[rows], ref[rows]) < 1e-10, i
 
 
+def test_dof_recovery_against_oracle():
+    """Recovery at the granularity of single DoFs (observation points): the
+    selected torn rows equal the full solve's bit for bit and the oracle's
+    solution within 1e-10 per column."""
+    c = cached_case("cube18u")
+    s = _solver(c)
+    offs = np.cumsum([0] + [d.n for d in c.domains])
+    rng = np.random.default_rng(1802)
+    rows = np.concatenate([offs[1] + rng.choice(c.domains[1].n, 40, replace=False),
+                           offs[5] + rng.choice(c.domains[5].n, 40, replace=False), [offs[-1] - 1]])
+    print(f"[parity] dof recovery cube18u: {len(rows)} rows in 3 domains", flush=True)
+    f = _rhs(c)
+    out = s.solve_dofs(f, rows).cpu().numpy()
+    full = s.solve(f).cpu().numpy()
+    assert np.array_equal(out, full[rows])
+    ref = oracle.serial_dd(c)["u"][rows]
+    assert _colerr(out, ref) < 1e-10
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 def test_graph_only_orderings(precision):
     """No DoF coordinates: every domain and the auxiliary block graph are
