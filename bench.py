@@ -41,8 +41,18 @@ WORKLOADS = {
                "axis cuts of 6..14 elements, eps_r U[1,8] tan-delta 0.02, 64 complex-normal RHS",
     "cube96j": "96^3 Nedelec-hex curl-curl, nodes jittered +/-0.2h (2,599,200 unknowns), 8^3 domains of 12^3, "
                "eps_r U[1,4] tan-delta 0.01, 256 complex-normal RHS (FP32 fronts + FP64 refinement)",
+    "tet40s": "Whitney-tet curl-curl on a jittered 40^3 Kuhn mesh carved to a ball (223,907 unknowns), dielectric "
+              "sphere eps_r 4 in eps_r 1, tan-delta 0.02, 64 domains from the graph partitioner, 8 complex-normal RHS",
 }
-MESH_N = {"cube48": 48, "cube24": 24, "cube64j": 64, "cube96j": 96}
+MESH_N = {"cube48": 48, "cube24": 24, "cube64j": 64, "cube96j": 96}   # cube meshes (global direct model)
+
+
+def make_workload(name):
+    if name.startswith("tet"):
+        from paper_2002_05019_amd.tetmesh import make_tet_case
+        return make_tet_case(name)
+    from paper_2002_05019_amd.problem import make_case
+    return make_case(name)
 
 
 def log(*a):
@@ -384,14 +394,13 @@ def main():
     tiles = [int(t) for t in args.tiles.split(",")] if args.tiles else None
     import numpy as np
     from paper_2002_05019_amd.binding import Solver
-    from paper_2002_05019_amd.problem import make_case
 
     t0 = time.perf_counter()
-    case = make_case(args.workload)
+    case = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: {case.n_global} unknowns, {case.n_dom} domains, "
         f"{case.n_mult} multipliers, generated in {time.perf_counter() - t0:.1f} s")
     nrhs = case.spec.nrhs
-    big = MESH_N[args.workload] >= 96
+    big = MESH_N.get(args.workload, 0) >= 96
     paths = ["fp32_refine"] if (args.no_fp64 or big) else ["fp64", "fp32_refine"]
     # host-only symbolic phase: flop counts (and the CPU baseline, which runs
     # before anything touches the GPU)
@@ -412,7 +421,7 @@ def main():
     value = flops / (ms * 1e-3) / 1e12
     kt = mx.get("kt")
     achieved = kt["flops"] / kt["seconds"] / 1e12 if kt and kt["seconds"] > 0 else None
-    dm = global_direct_model(MESH_N[args.workload])
+    dm = global_direct_model(MESH_N[args.workload]) if args.workload in MESH_N else None
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -445,11 +454,12 @@ def main():
                                  "achieved": round(bs / ts / 1e9, 1), "peak": HBM_GBS, "unit": "GB/s",
                                  "frac": round(bs / ts / 1e9 / HBM_GBS, 4), "bytes_per_solve": bs}
     out["memory"] = {"workspace_gb_mixed": out["mixed"]["workspace_gb"],
-                     "factor_gb_mixed": out["mixed"]["factor_gb"],
-                     "global_direct_fp64_gb": round(dm["nnz"] * 16 / 1e9, 3),
-                     "global_direct_fp64_flops": dm["fma"] * 8,
-                     "global_direct_note": "undecomposed sparse LDL^T of the same mesh, geometric nested "
-                                           "dissection model, complex FP64 (16 B per factor entry)"}
+                     "factor_gb_mixed": out["mixed"]["factor_gb"]}
+    if dm is not None:
+        out["memory"].update({"global_direct_fp64_gb": round(dm["nnz"] * 16 / 1e9, 3),
+                              "global_direct_fp64_flops": dm["fma"] * 8,
+                              "global_direct_note": "undecomposed sparse LDL^T of the same mesh, geometric nested "
+                                                    "dissection model, complex FP64 (16 B per factor entry)"})
     if "fp64" in res:
         out["memory"]["workspace_gb_fp64"] = out["fp64"]["workspace_gb"]
         out["memory"]["factor_gb_fp64"] = out["fp64"]["factor_gb"]
