@@ -2379,45 +2379,64 @@ __global__ void k_xinv_out(KP<T> p, int f_id, cd *out) {
   out[e] = cd{(double)X[e], (double)X[e + g * g]};
 }
 
-// FP64 refinement state: U (torn x mr planar doubles), L (mult x mr planar)
+// FP64 refinement state: U, torn rows x mr columns with a row's columns
+// contiguous (complex interleaved: the residual's gathers of a row read one
+// run of the columns), and L, multipliers x mr planar column-major.
+// U from / plus the internal column-major planar solution x: 64-row x
+// 8-column tiles through LDS, coalesced on both sides (mode 0: U = x, 1: U += x).
 template <typename T>
-__global__ void k_r_init(KP<T> p, int nrhs) {
-  const int64_t mr = p.mr;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t nt = p.n_torn * nrhs, nm = p.n_mult * nrhs;
-  double *U = p.r64;
-  double *L = U + 2 * p.n_torn * mr;
-  if (e < nt) {
-    const int64_t r = e % p.n_torn, j = e / p.n_torn;
-    const T *x = p.num + p.vx;
-    U[r + j * p.n_torn] = x[r + j * p.n_torn];
-    U[r + j * p.n_torn + p.n_torn * mr] = x[r + j * p.n_torn + p.n_torn * mr];
-  } else if (e < nt + nm) {
-    const int64_t q = e - nt, m = q % p.n_mult, j = q / p.n_mult;
-    const T *l = p.num + p.vl;
-    L[m + j * p.n_mult] = l[m + j * p.n_mult];
-    L[m + j * p.n_mult + p.n_mult * mr] = l[m + j * p.n_mult + p.n_mult * mr];
+__global__ __launch_bounds__(256) void k_r_utile(KP<T> p, int nrhs, int mode) {
+  if (mode && gated(p)) return;
+  __shared__ double sr[64][9], si[64][9];
+  const int64_t nt = p.n_torn, mr = p.mr;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 8;
+  const T *x = p.num + p.vx;
+  for (int e = threadIdx.x; e < 512; e += 256) {
+    const int j = e >> 6, rr = e & 63;
+    const int64_t r = r0 + rr;
+    double a = 0, b = 0;
+    if (r < nt && j0 + j < nrhs) {
+      a = (double)x[r + (int64_t)(j0 + j) * nt];
+      b = (double)x[r + (int64_t)(j0 + j) * nt + nt * mr];
+    }
+    sr[rr][j] = a;
+    si[rr][j] = b;
+  }
+  __syncthreads();
+  cd *U = (cd *)p.r64;
+  for (int e = threadIdx.x; e < 512; e += 256) {
+    const int rr = e >> 3, j = e & 7;
+    const int64_t r = r0 + rr;
+    if (r < nt && j0 + j < nrhs) {
+      cd &u = U[r * mr + j0 + j];
+      if (mode) {
+        u.re += sr[rr][j];
+        u.im += si[rr][j];
+      } else {
+        u = cd{sr[rr][j], si[rr][j]};
+      }
+    }
   }
 }
 
+// L from / plus the internal multipliers (mode 0: L = l, 1: L += l)
 template <typename T>
-__global__ void k_r_update(KP<T> p, int nrhs) {
-  if (gated(p)) return;
+__global__ void k_r_lpart(KP<T> p, int nrhs, int mode) {
+  if (mode && gated(p)) return;
   const int64_t mr = p.mr;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t nt = p.n_torn * nrhs, nm = p.n_mult * nrhs;
-  double *U = p.r64;
-  double *L = U + 2 * p.n_torn * mr;
-  if (e < nt) {
-    const int64_t r = e % p.n_torn, j = e / p.n_torn;
-    const T *x = p.num + p.vx;
-    U[r + j * p.n_torn] += (double)x[r + j * p.n_torn];
-    U[r + j * p.n_torn + p.n_torn * mr] += (double)x[r + j * p.n_torn + p.n_torn * mr];
-  } else if (e < nt + nm) {
-    const int64_t q = e - nt, m = q % p.n_mult, j = q / p.n_mult;
-    const T *l = p.num + p.vl;
-    L[m + j * p.n_mult] += (double)l[m + j * p.n_mult];
-    L[m + j * p.n_mult + p.n_mult * mr] += (double)l[m + j * p.n_mult + p.n_mult * mr];
+  if (e >= p.n_mult * nrhs) return;
+  double *L = p.r64 + 2 * p.n_torn * mr;
+  const int64_t m = e % p.n_mult, j = e / p.n_mult;
+  const T *l = p.num + p.vl;
+  const double a = (double)l[m + j * p.n_mult], b = (double)l[m + j * p.n_mult + p.n_mult * mr];
+  if (mode) {
+    L[m + j * p.n_mult] += a;
+    L[m + j * p.n_mult + p.n_mult * mr] += b;
+  } else {
+    L[m + j * p.n_mult] = a;
+    L[m + j * p.n_mult + p.n_mult * mr] = b;
   }
 }
 
@@ -2442,8 +2461,8 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
   if (gated(p)) return;
   __shared__ double red[8][256];
   const int64_t mr = p.mr;
-  const double *U = p.r64;
-  const double *L = U + 2 * p.n_torn * mr;
+  const cd *Uc = (const cd *)p.r64;
+  const double *L = p.r64 + 2 * p.n_torn * mr;
   double *part = p.r64 + part_off;
   const int64_t nrow = p.n_torn + p.n_mult;
   const int64_t nt = p.n_torn, nm = p.n_mult;
@@ -2465,12 +2484,15 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
         // gr, gi: the same row of f - K u~, u~ taking every DoF's value from
         // its representative copy; summed over the copies of a DoF this is
         // the residual of the assembled (undecomposed) system
+        // (gr, gi: the correction -K (u~ - u), nonzero only through columns
+        // whose representative is another copy, i.e. interface DoFs)
         double gr[8], gi[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const cd fv = f[e + jc[q] * ldf];
-          rr[q] = gr[q] = fv.re;
-          ri[q] = gi[q] = fv.im;
+          rr[q] = fv.re;
+          ri[q] = fv.im;
+          gr[q] = gi[q] = 0;
         }
         if (!fnorm) {
           // SELL-64: the wave's 64 rows form one slice, entry k of all its
@@ -2481,21 +2503,35 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
             const cd a = p.vals[z];
             const int64_t c = p.sellc[z];
             const int64_t cg = p.grep[c];
-            double ur[8], ui[8], vr[8], vi[8];
+            // the pass's columns of row c: one contiguous run
+            const cd *uc = Uc + c * mr;
+            double ur[8], ui[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-              ur[q] = U[c + jc[q] * nt];
-              ui[q] = U[c + jc[q] * nt + nt * mr];
-              vr[q] = U[cg + jc[q] * nt];
-              vi[q] = U[cg + jc[q] * nt + nt * mr];
+              const cd x = uc[jc[q]];
+              ur[q] = x.re;
+              ui[q] = x.im;
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               rr[q] -= a.re * ur[q] - a.im * ui[q];
               ri[q] -= a.re * ui[q] + a.im * ur[q];
-              gr[q] -= a.re * vr[q] - a.im * vi[q];
-              gi[q] -= a.re * vi[q] + a.im * vr[q];
             }
+            if (cg != c) {
+              const cd *ug = Uc + cg * mr;
+#pragma unroll
+              for (int q = 0; q < 8; ++q) {
+                const cd y = ug[jc[q]];
+                const double dr = y.re - ur[q], di = y.im - ui[q];
+                gr[q] -= a.re * dr - a.im * di;
+                gi[q] -= a.re * di + a.im * dr;
+              }
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            gr[q] += rr[q];
+            gi[q] += ri[q];
           }
           const int gidx = p.rowgam[e];
           if (gidx >= 0) {
@@ -2518,6 +2554,13 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
               vf[e + (j0 + q) * nt + nt * mr] = (T)ri[q];
             }
         }
+        if (fnorm) {   // the right-hand side itself
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            gr[q] = rr[q];
+            gi[q] = ri[q];
+          }
+        }
         double *G = p.r64 + p.rg;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -2534,8 +2577,9 @@ __global__ __launch_bounds__(256) void k_r_resid(KP<T> p, const cd *f, int64_t l
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             const double sg = R.sg[t];
-            rr[q] -= sg * U[R.row[t] + jc[q] * nt];
-            ri[q] -= sg * U[R.row[t] + jc[q] * nt + nt * mr];
+            const cd x = Uc[R.row[t] * mr + jc[q]];
+            rr[q] -= sg * x.re;
+            ri[q] -= sg * x.im;
           }
           if (q < nj) {
             vc[m + (j0 + q) * nm] = (T)rr[q];
@@ -2666,20 +2710,39 @@ __global__ void k_r_ctl_reset(int *ctl) {
   if (threadIdx.x < 4) ctl[threadIdx.x] = 0;
 }
 
+// U -> the caller's u (column-major, leading dimension ldu): 64-row x
+// 8-column tiles through LDS
 template <typename T>
-__global__ void k_r_out(KP<T> p, cd *u, int64_t ldu, cd *lam, int64_t ldl, int nrhs) {
-  const int64_t mr = p.mr;
-  const double *U = p.r64;
-  const double *L = U + 2 * p.n_torn * mr;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t nt = p.n_torn * nrhs, nm = p.n_mult * nrhs;
-  if (e < nt) {
-    const int64_t r = e % p.n_torn, j = e / p.n_torn;
-    u[r + j * ldu] = cd{U[r + j * p.n_torn], U[r + j * p.n_torn + p.n_torn * mr]};
-  } else if (lam && e < nt + nm) {
-    const int64_t q = e - nt, m = q % p.n_mult, j = q / p.n_mult;
-    lam[m + j * ldl] = cd{L[m + j * p.n_mult], L[m + j * p.n_mult + p.n_mult * mr]};
+__global__ __launch_bounds__(256) void k_r_uout(KP<T> p, cd *u, int64_t ldu, int nrhs) {
+  __shared__ double sr[64][9], si[64][9];
+  const int64_t nt = p.n_torn, mr = p.mr;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 8;
+  const cd *U = (const cd *)p.r64;
+  for (int e = threadIdx.x; e < 512; e += 256) {
+    const int rr = e >> 3, j = e & 7;
+    const int64_t r = r0 + rr;
+    cd x = cd{0, 0};
+    if (r < nt && j0 + j < nrhs) x = U[r * mr + j0 + j];
+    sr[rr][j] = x.re;
+    si[rr][j] = x.im;
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 512; e += 256) {
+    const int j = e >> 6, rr = e & 63;
+    const int64_t r = r0 + rr;
+    if (r < nt && j0 + j < nrhs) u[r + (int64_t)(j0 + j) * ldu] = cd{sr[rr][j], si[rr][j]};
+  }
+}
+
+template <typename T>
+__global__ void k_r_lout(KP<T> p, cd *lam, int64_t ldl, int nrhs) {
+  const int64_t mr = p.mr;
+  const double *L = p.r64 + 2 * p.n_torn * mr;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= p.n_mult * nrhs) return;
+  const int64_t m = e % p.n_mult, j = e / p.n_mult;
+  lam[m + j * ldl] = cd{L[m + j * p.n_mult], L[m + j * p.n_mult + p.n_mult * mr]};
 }
 
 // ---------------------------------------------------------------------------
@@ -2927,16 +2990,21 @@ hipError_t operator_copy(const Plan &P, uint8_t *ws, const void *vals, hipStream
                      (cd *)(ws + P.b_vals));
   return hipGetLastError();
 }
-hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st) {
-  KP<float> k = make_kp<float>(P, ws, ws + P.b_vals);
-  hipLaunchKernelGGL(k_r_init<float>, dim3(nblk((P.n_torn + P.n_mult) * nrhs)), dim3(256), 0, st, k, nrhs);
-  return hipGetLastError();
-}
-hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st, const int *gate) {
+static hipError_t refine_state(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st, const int *gate, int mode) {
   KP<float> k = make_kp<float>(P, ws, ws + P.b_vals);
   k.skip = gate;
-  hipLaunchKernelGGL(k_r_update<float>, dim3(nblk((P.n_torn + P.n_mult) * nrhs)), dim3(256), 0, st, k, nrhs);
+  if (P.n_torn > 0)
+    hipLaunchKernelGGL(k_r_utile<float>, dim3((unsigned)((P.n_torn + 63) / 64), (unsigned)((nrhs + 7) / 8)),
+                       dim3(256), 0, st, k, nrhs, mode);
+  if (P.n_mult > 0)
+    hipLaunchKernelGGL(k_r_lpart<float>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, nrhs, mode);
   return hipGetLastError();
+}
+hipError_t refine_init(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st) {
+  return refine_state(P, ws, nrhs, st, nullptr, 0);
+}
+hipError_t refine_update(const Plan &P, uint8_t *ws, int nrhs, hipStream_t st, const int *gate) {
+  return refine_state(P, ws, nrhs, st, gate, 1);
 }
 hipError_t refine_resid(const Plan &P, uint8_t *ws, const void *f, int64_t ldf, int nrhs, bool fnorm,
                         hipStream_t st, const int *gate) {
@@ -2968,8 +3036,11 @@ hipError_t refine_test(const Plan &P, uint8_t *ws, int nrhs, double tol, bool co
 hipError_t refine_out(const Plan &P, uint8_t *ws, void *u, int64_t ldu, void *lam, int64_t ldl, int nrhs,
                       hipStream_t st) {
   KP<float> k = make_kp<float>(P, ws, ws + P.b_vals);
-  hipLaunchKernelGGL(k_r_out<float>, dim3(nblk((P.n_torn + P.n_mult) * nrhs)), dim3(256), 0, st, k, (cd *)u, ldu,
-                     (cd *)lam, ldl, nrhs);
+  if (P.n_torn > 0)
+    hipLaunchKernelGGL(k_r_uout<float>, dim3((unsigned)((P.n_torn + 63) / 64), (unsigned)((nrhs + 7) / 8)),
+                       dim3(256), 0, st, k, (cd *)u, ldu, nrhs);
+  if (lam && P.n_mult > 0)
+    hipLaunchKernelGGL(k_r_lout<float>, dim3(nblk(P.n_mult * nrhs)), dim3(256), 0, st, k, (cd *)lam, ldl, nrhs);
   return hipGetLastError();
 }
 
