@@ -525,19 +525,26 @@ __global__ __launch_bounds__(256) void k_store(KP<T> p, int64_t first) {
 // FP64, with L^-1 formed alongside (section II: pivot search confined to the
 // diagonal block).
 //
-// The tile lives in registers, 2-D cyclic over the threads: thread (tr, tc)
-// holds entries (tr + 16u, tc + TC v), both triangles, in their original
-// (physical) positions.  Interchanges are never carried out on the data: the
-// logical order is a permutation kept per lane (lane a of every wave holds the
-// physical index of position a), and every thread keeps bits for its rows and
-// columns that are still active.  One register set M serves both matrices: an
-// active column holds the partially reduced tile A, an eliminated column holds
-// the corresponding column of L^-1 (the two never need updating at the same
-// entry; rows of eliminated pivots keep stale values in active columns, which
-// are never read).  The owners of the next pivot's column and row publish it
-// in LDS (masked and with the diagonal's reciprocal) at the end of each step;
-// every wave repeats the pivot test on it, and a step that keeps its diagonal
-// pivot needs one barrier.
+// The tile lives in registers, lane c of wave w holding column c, rows
+// 16 w .. 16 w + 15 (four waves, one per SIMD), both triangles, in their
+// original (physical) positions.  Interchanges are never carried out on the
+// data: the order is a permutation kept per lane (positions pv, pos), and the
+// active rows / columns are one 64-bit mask, uniform over the block.  One
+// register set M serves both matrices: an active column holds the partially
+// reduced tile A, an eliminated column the corresponding column of L^-1 (the
+// two never need updating at the same entry; rows of eliminated pivots keep
+// stale values in active columns, which are never read).
+//
+// A step publishes the pivot's row once: its owner wave writes its register of
+// that row, one value per lane, in two forms (masked to the active columns
+// other than the pivot: the pivot test and the multipliers of every wave's
+// rows; raw with 1 at the pivot: the update row).  Every wave repeats the
+// pivot test on it and updates all of its 16 x 64 entries as
+// M(r, c) = keep(c) M(r, c) - cm(r) w(c), w = D^-1 z, keep = 0 on the pivot
+// columns, which thereby become their columns of -L (of L^-1).  A step that
+// keeps its diagonal pivot needs one barrier.  At most 128 registers, so that
+// a workgroup is seated as soon as one workgroup of the trailing update that
+// shares the CUs retires.
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
@@ -556,8 +563,6 @@ __device__ __forceinline__ double wave_max(double v) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
                           __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
-// threads of the pivot-tile kernel
-constexpr int PANEL_NT = 512;
 // 1/x from the hardware reciprocal and one Newton step (a short dependency
 // chain; x = 0 gives a non-finite result, which the callers test for)
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -565,213 +570,155 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
-  // NT threads: rows tr + 16u (u < 4), columns tc + TC v (v < CV)
-  constexpr int TC = NT / 16, CV = NB / TC, NW = NT / 64;
-  static_assert(NT == 256 || NT == 512 || NT == 1024, "tile thread grid");
-  // owner column group and register slot of a (non-negative) tile index:
-  // unsigned, so they compile to a mask and a shift
-  auto qc = [](int q) { return (int)((unsigned)q % TC); };
-  auto qv = [](int q) { return (int)((unsigned)q / TC); };
-  // A published pivot p: masked column (A(i, p) on active rows i != p, else
-  // 0), the update row z (A(c, p) on active columns, 1 at p, L^-1(p, c) on
-  // eliminated columns), the diagonal A(p, p) and its reciprocal.
-  // Buffers 0/1: the next 1 x 1 pivot (double-buffered); buffer 2: the
-  // candidate of a rejected diagonal.
-  __shared__ double cmr[3][NB], cmi[3][NB], zvr[3][NB], zvi[3][NB], dgs[3][4];
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_panel(KP<T> p, int64_t first) {
+  __shared__ double2 zrow[3][NB], cmrow[3][NB];
+  __shared__ double dgs[3][4];
   __shared__ double dvr[NB], dvi[NB], dor[NB], doi[NB];
-  __shared__ int pdl[NB], inv[NB];
-  __shared__ double red[NW];
+  __shared__ int pdl[NB];
+  __shared__ double red[4];
 
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int k = it.k, n = f.n, b = min(NB, f.s - k), tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4, lane = tid & 63;
+  const int k = it.k, n = f.n, b = min(NB, f.s - k), tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r0 = 16 * w;   // first row of this wave
   T *fr = p.num + f.off;
   T *fi = fr + (int64_t)n * n;
   constexpr double ALPHA = 0.6403882032022076;   // (1 + sqrt(17)) / 8
 
-  double mr[4][CV], mi[4][CV];
+  double mr[16], mi[16];
   double amax = 0;
-  unsigned rowbits = 0, colbits = 0;   // active rows u / columns v of this thread
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < CV; ++v) {
-      const int i = tr + 16 * u, c = tc + TC * v;
-      double xr = 0, xi = 0;
-      if (i < b && c < b) {
-        const int64_t o = (k + max(i, c)) + (int64_t)(k + min(i, c)) * n;
-        xr = (double)fr[o];
-        xi = (double)fi[o];
-      }
-      mr[u][v] = xr;
-      mi[u][v] = xi;
-      amax = fmax(amax, cabs1(xr, xi));
-      if (i < b) rowbits |= 1u << u;
-      if (c < b) colbits |= 1u << v;
+  for (int t = 0; t < 16; ++t) {
+    const int i = r0 + t;
+    double xr = 0, xi = 0;
+    if (i < b && lane < b) {
+      const int64_t o = (k + max(i, lane)) + (int64_t)(k + min(i, lane)) * n;
+      xr = (double)fr[o];
+      xi = (double)fi[o];
     }
+    mr[t] = xr;
+    mi[t] = xi;
+    amax = fmax(amax, cabs1(xr, xi));
+  }
   amax = wave_max(amax);
-  if (lane == 0) red[tid >> 6] = amax;
+  if (lane == 0) red[w] = amax;
 
-  // publishes pivot q (block-uniform) into buffer s; the register slot is
-  // picked by selects (no dynamic register indexing)
+  unsigned long long act = b == 64 ? ~0ull : ((1ull << b) - 1);   // active physical rows / columns
+  // row q (block-uniform) with values (xr, xi) in this lane's column, into
+  // buffer s: masked to the active columns other than q, raw with 1 at q,
+  // and the diagonal with its reciprocal
+  auto put_row = [&](int q, int s, double xr, double xi) {
+    const bool a = ((act >> lane) & 1) && lane != q;
+    cmrow[s][lane] = a ? make_double2(xr, xi) : make_double2(0.0, 0.0);
+    zrow[s][lane] = lane == q ? make_double2(1.0, 0.0) : make_double2(xr, xi);
+    if (lane == q) {
+      const double rd = rcp_nr(fma(xr, xr, xi * xi));
+      dgs[s][0] = xr;
+      dgs[s][1] = xi;
+      dgs[s][2] = xr * rd;
+      dgs[s][3] = -xi * rd;
+    }
+  };
+  // register of row q in this wave, -1 if another wave holds it (uniform)
+  auto slot_of = [&](int q) { return w == (q >> 4) ? (q & 15) : -1; };
+  // publishes row q from registers: one uniform branch per register (no
+  // dynamic register index)
   auto publish = [&](int q, int s) {
-    if (tc == qc(q)) {
-      const int w = qv(q);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        double xr = mr[u][0], xi = mi[u][0];
-#pragma unroll
-        for (int v = 1; v < CV; ++v) {
-          xr = w == v ? mr[u][v] : xr;
-          xi = w == v ? mi[u][v] : xi;
-        }
-        const int i = tr + 16 * u;
-        const bool act = ((rowbits >> u) & 1) && i != q;
-        cmr[s][i] = act ? xr : 0.0;
-        cmi[s][i] = act ? xi : 0.0;
-        if (act) {
-          zvr[s][i] = xr;
-          zvi[s][i] = xi;
-        }
-        if (i == q) {
-          const double rd = rcp_nr(fma(xr, xr, xi * xi));
-          dgs[s][0] = xr;
-          dgs[s][1] = xi;
-          dgs[s][2] = xr * rd;
-          dgs[s][3] = -xi * rd;
-        }
+    const int qt = slot_of(q);
+    if (qt < 0) return;
+    // binary search over the register index (uniform branches)
+    if (qt < 8) {
+      if (qt < 4) {
+        if (qt < 2) { if (qt == 0) put_row(q, s, mr[0], mi[0]); else put_row(q, s, mr[1], mi[1]); }
+        else { if (qt == 2) put_row(q, s, mr[2], mi[2]); else put_row(q, s, mr[3], mi[3]); }
+      } else {
+        if (qt < 6) { if (qt == 4) put_row(q, s, mr[4], mi[4]); else put_row(q, s, mr[5], mi[5]); }
+        else { if (qt == 6) put_row(q, s, mr[6], mi[6]); else put_row(q, s, mr[7], mi[7]); }
+      }
+    } else {
+      if (qt < 12) {
+        if (qt < 10) { if (qt == 8) put_row(q, s, mr[8], mi[8]); else put_row(q, s, mr[9], mi[9]); }
+        else { if (qt == 10) put_row(q, s, mr[10], mi[10]); else put_row(q, s, mr[11], mi[11]); }
+      } else {
+        if (qt < 14) { if (qt == 12) put_row(q, s, mr[12], mi[12]); else put_row(q, s, mr[13], mi[13]); }
+        else { if (qt == 14) put_row(q, s, mr[14], mi[14]); else put_row(q, s, mr[15], mi[15]); }
       }
     }
-    if (tr == (q & 15)) {
-      const int w = q >> 4;
-#pragma unroll
-      for (int v = 0; v < CV; ++v) {
-        double xr = mr[0][v], xi = mi[0][v];
-#pragma unroll
-        for (int u = 1; u < 4; ++u) {
-          xr = w == u ? mr[u][v] : xr;
-          xi = w == u ? mi[u][v] : xi;
-        }
-        const int c = tc + TC * v;
-        if (c == q) {
-          zvr[s][c] = 1.0;
-          zvi[s][c] = 0.0;
-        } else if (!((colbits >> v) & 1)) {
-          zvr[s][c] = xr;
-          zvi[s][c] = xi;
-        }
-      }
-    }
-  };
-  // column q of M := 0 (it is about to receive -l, the new column of L^-1)
-  auto zero_col = [&](int q) {
-    if (tc == qc(q)) {
-      const int w = qv(q);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < CV; ++v) {
-          mr[u][v] = v == w ? 0.0 : mr[u][v];
-          mi[u][v] = v == w ? 0.0 : mi[u][v];
-        }
-    }
-  };
-  auto retire = [&](int q) {
-    if (tr == (q & 15)) rowbits &= ~(1u << (q >> 4));
-    if (tc == qc(q)) colbits &= ~(1u << qv(q));
   };
 
-  int pv = lane;   // physical row at position `lane`
-  int npert = 0, n2 = 0, nswap = 0;   // perturbed pivots, 2 x 2 pivots, interchanges
+  int pv = lane, pos = lane;   // physical index at position `lane`; position of physical `lane`
+  int npert = 0, n2 = 0, nswap = 0;
   int j = 0, cur = 0;
   publish(0, 0);
   __syncthreads();
-  double tmax = red[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) tmax = fmax(tmax, red[w]);
+  const double tmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   const double tau = tmax > 0 ? 1e-12 * tmax : 1.0;
 
   while (j < b) {
-    // pivot pv[j] is published in buffer `cur`
     const int pj = __builtin_amdgcn_readlane(pv, j);
-    int s = cur;   // buffer of the pivot actually used
-    // pivot test over positions j.. (physical rows pv), repeated by every
-    // wave; the column maximum is needed only if some entry rejects the
-    // diagonal.  LDS loads are unconditional and selected afterwards.
-    const double absakk = cabs1(dgs[cur][0], dgs[cur][1]);
-    // operands of a diagonal step, fetched ahead of the test (dependent
-    // FP64 latency, not issue, bounds this kernel)
-    double cr[4], ci[4], xzr[CV], xzi[CV];
+    double2 z = zrow[cur][lane];
+    const double2 cmc = cmrow[cur][lane];
     double ir = dgs[cur][2], ii = dgs[cur][3];
-    bool zpiv = dgs[cur][0] == 0.0 && dgs[cur][1] == 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      cr[u] = cmr[cur][tr + 16 * u];
-      ci[u] = cmi[cur][tr + 16 * u];
-    }
-#pragma unroll
-    for (int v = 0; v < CV; ++v) {
-      xzr[v] = zvr[cur][tc + TC * v];
-      xzi[v] = zvi[cur][tc + TC * v];
-    }
-    const bool cand = lane > j && lane < b;
-    const double cvx = cabs1(cmr[cur][pv], cmi[cur][pv]);
-    const double cv = cand ? cvx : -1.0;
-    int kind = 1, piv = j;
-    if (__ballot(cand && absakk < ALPHA * cv)) {
+    const double d0r = dgs[cur][0], d0i = dgs[cur][1];
+    const double2 *cmp = cmrow[cur] + r0;   // multipliers of this wave's rows
+    bool zpiv = d0r == 0.0 && d0i == 0.0;
+    const double absakk = cabs1(d0r, d0i);
+    const double cv = cabs1(cmc.x, cmc.y);   // 0 off the active rows and at pj
+    int kind = 1, pp = pj, pm = pj;
+    if (__ballot(absakk < ALPHA * cv)) {
       const double colmax = wave_max(cv);
-      // lowest position attaining the column maximum
-      const int imax = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)__ballot(cand && cv == colmax)) - 1);
-      const int pm = __builtin_amdgcn_readlane(pv, imax);
+      pm = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)__ballot(cv == colmax)) - 1);
+      pm = pm < 0 ? pj : pm;   // (a lane attains the maximum unless the values are not finite)
       publish(pm, 2);
       __syncthreads();
-      // row imax of A over positions j.. = column pm on the active rows
-      const double rvx = cabs1(cmr[2][pv], cmi[2][pv]);
-      const double rv = (lane >= j && lane < b && lane != imax) ? rvx : -1.0;
-      const double rowmax = wave_max(rv);
+      const double2 c2 = cmrow[2][lane];
+      const double rowmax = wave_max(cabs1(c2.x, c2.y));
+      const double e0 = dgs[2][0], e1 = dgs[2][1];
       if (absakk * rowmax >= ALPHA * colmax * colmax) {
         kind = 1;
-        piv = j;
-      } else if (cabs1(dgs[2][0], dgs[2][1]) >= ALPHA * rowmax) {
+      } else if (cabs1(e0, e1) >= ALPHA * rowmax) {
         kind = 1;
-        piv = imax;
+        pp = pm;
       } else {
         kind = 2;
-        piv = imax;
       }
       kind = __builtin_amdgcn_readfirstlane(kind);
-      piv = __builtin_amdgcn_readfirstlane(piv);
-      const int q = kind == 1 ? j : j + 1;
-      nswap += piv != q;
-      n2 += kind == 2;
-      if (piv != q) {
-        // interchange of positions q and piv: only the order changes
-        const int a0 = __builtin_amdgcn_readlane(pv, q), a1 = __builtin_amdgcn_readlane(pv, piv);
-        pv = lane == q ? a1 : (lane == piv ? a0 : pv);
+      pp = __builtin_amdgcn_readfirstlane(pp);
+      if (kind == 2 || pp == pm) {
+        // interchange of positions q and that of pm: only the order changes
+        const int q = kind == 1 ? j : j + 1;
+        const int ip = __builtin_amdgcn_readlane(pos, pm);
+        if (ip != q) {
+          const int a0 = __builtin_amdgcn_readlane(pv, q);
+          pv = lane == q ? pm : (lane == ip ? a0 : pv);
+          pos = lane == pm ? q : (lane == a0 ? ip : pos);
+          ++nswap;
+        }
       }
-      if (kind == 1 && piv != q) {
-        // new pivot pm: its data is in buffer 2
-        s = 2;
+      if (kind == 1 && pp == pm) {
+        cmp = cmrow[2] + r0;
+        z = zrow[2][lane];
         ir = dgs[2][2];
         ii = dgs[2][3];
-        zpiv = dgs[2][0] == 0.0 && dgs[2][1] == 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          cr[u] = cmr[2][tr + 16 * u];
-          ci[u] = cmi[2][tr + 16 * u];
+        zpiv = e0 == 0.0 && e1 == 0.0;
+      }
+      if (kind == 2) {
+        // the two pivot rows take no update: clear pm's multiplier in pj's
+        // row and pj's in pm's (every wave has read its test values)
+        if (tid == 0) {
+          cmrow[cur][pm] = make_double2(0.0, 0.0);
+          cmrow[2][pj] = make_double2(0.0, 0.0);
         }
-#pragma unroll
-        for (int v = 0; v < CV; ++v) {
-          xzr[v] = zvr[2][tc + TC * v];
-          xzi[v] = zvi[2][tc + TC * v];
-        }
+        __syncthreads();
       }
     }
+    // the update, one pass per pivot row: M(r, c) = keep(c) M(r, c) - cm(r) w(c)
+    const double2 *cmb = cmrow[2] + r0;   // second pass: the second row of a 2 x 2 pivot
+    double wr, wi, w2r = 0, w2i = 0, keep;
+    int npass = 1;
     if (kind == 1) {
-      const int pp = s == 2 ? __builtin_amdgcn_readlane(pv, j) : pj;
       if (zpiv) {
         ir = 1.0 / tau;
         ii = 0.0;
@@ -780,30 +727,17 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
       if (tid == 0) {
         dvr[j] = ir; dvi[j] = ii; dor[j] = 0; doi[j] = 0; pdl[j] = 0;
       }
-      // active rows r: M(r, c) -= A(r, pp) d^-1 z(c); the column pp becomes
-      // L^-1(:, pp) = -l.  Rows already eliminated (masked column 0) keep
-      // their L^-1 entries; their entries in active columns are stale and
-      // never read again.
-      double zr[CV], zi[CV];
-#pragma unroll
-      for (int v = 0; v < CV; ++v) {
-        zr[v] = xzr[v] * ir - xzi[v] * ii;
-        zi[v] = xzr[v] * ii + xzi[v] * ir;
-      }
-      zero_col(pp);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < CV; ++v) {
-          mr[u][v] = fma(-cr[u], zr[v], fma(ci[u], zi[v], mr[u][v]));
-          mi[u][v] = fma(-cr[u], zi[v], fma(-ci[u], zr[v], mi[u][v]));
-        }
-      retire(pp);
+      wr = z.x * ir - z.y * ii;
+      wi = z.x * ii + z.y * ir;
+      keep = lane == pp ? 0.0 : 1.0;
+      act &= ~(1ull << pp);
       j += 1;
     } else {
-      // 2 x 2 pivot (pj, p1): pj in buffer cur, p1 (= pm) in buffer 2
-      const int p1 = __builtin_amdgcn_readlane(pv, j + 1);
-      double ar_ = dgs[cur][0], ai_ = dgs[cur][1], cr_ = cmr[cur][p1], ci_ = cmi[cur][p1];
+      // 2 x 2 pivot (pj, pm) at positions j, j + 1
+      const double2 zc = zrow[cur][lane], zm = zrow[2][lane];
+      double ar_ = d0r, ai_ = d0i;
+      const double2 cc = zrow[cur][pm];
+      const double cr_ = cc.x, ci_ = cc.y;
       double er_ = dgs[2][0], ei_ = dgs[2][1];
       double detr = (ar_ * er_ - ai_ * ei_) - (cr_ * cr_ - ci_ * ci_);
       double deti = (ar_ * ei_ + ai_ * er_) - 2.0 * cr_ * ci_;
@@ -815,8 +749,7 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
         ++npert;
       }
       const double rden = rcp_nr(fma(detr, detr, deti * deti));
-      const double idr = detr * rden, idi = -deti * rden;   // 1/det
-      // D^-1 = [[e, -c], [-c, a]] / det
+      const double idr = detr * rden, idi = -deti * rden;
       const double d00r = er_ * idr - ei_ * idi, d00i = er_ * idi + ei_ * idr;
       const double d11r = ar_ * idr - ai_ * idi, d11i = ar_ * idi + ai_ * idr;
       const double d01r = -(cr_ * idr - ci_ * idi), d01i = -(cr_ * idi + ci_ * idr);
@@ -825,48 +758,45 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
         dor[j] = d01r; doi[j] = d01i; dor[j + 1] = d01r; doi[j + 1] = d01i;
         pdl[j] = 1; pdl[j + 1] = -1;
       }
-      retire(pj);
-      retire(p1);
-      // active rows r: M(r, c) -= l0(r) z0(c) + l1(r) z1(c),
-      // [l0 l1](r) = [A(r, pj) A(r, p1)] D^-1; z0 (z1) is the update row of
-      // pj (p1) with the other pivot's entry 0
-      double l0r[4], l0i[4], l1r[4], l1i[4], z0r[CV], z0i[CV], z1r[CV], z1i[CV];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool ok = (rowbits >> u) & 1;
-        const double t0r = cmr[cur][tr + 16 * u], t0i = cmi[cur][tr + 16 * u];
-        const double t1r = cmr[2][tr + 16 * u], t1i = cmi[2][tr + 16 * u];
-        const double a0r = ok ? t0r : 0.0, a0i = ok ? t0i : 0.0;
-        const double a1r = ok ? t1r : 0.0, a1i = ok ? t1i : 0.0;
-        l0r[u] = (a0r * d00r - a0i * d00i) + (a1r * d01r - a1i * d01i);
-        l0i[u] = (a0r * d00i + a0i * d00r) + (a1r * d01i + a1i * d01r);
-        l1r[u] = (a0r * d01r - a0i * d01i) + (a1r * d11r - a1i * d11i);
-        l1i[u] = (a0r * d01i + a0i * d01r) + (a1r * d11i + a1i * d11r);
-      }
-#pragma unroll
-      for (int v = 0; v < CV; ++v) {
-        const int c = tc + TC * v;
-        const double x0r = zvr[cur][c], x0i = zvi[cur][c], x1r = zvr[2][c], x1i = zvi[2][c];
-        z0r[v] = c == p1 ? 0.0 : x0r;
-        z0i[v] = c == p1 ? 0.0 : x0i;
-        z1r[v] = c == pj ? 0.0 : x1r;
-        z1i[v] = c == pj ? 0.0 : x1i;
-      }
-      zero_col(pj);
-      zero_col(p1);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < CV; ++v) {
-          double xr = mr[u][v], xi = mi[u][v];
-          xr = fma(-l0r[u], z0r[v], fma(l0i[u], z0i[v], xr));
-          xi = fma(-l0r[u], z0i[v], fma(-l0i[u], z0r[v], xi));
-          xr = fma(-l1r[u], z1r[v], fma(l1i[u], z1i[v], xr));
-          xi = fma(-l1r[u], z1i[v], fma(-l1i[u], z1r[v], xi));
-          mr[u][v] = xr;
-          mi[u][v] = xi;
-        }
+      // update rows z0 (pj's, 0 at pm) and z1 (pm's, 0 at pj), [w w2] = D^-1 [z0 z1]
+      const double z0r = lane == pm ? 0.0 : zc.x, z0i = lane == pm ? 0.0 : zc.y;
+      const double z1r = lane == pj ? 0.0 : zm.x, z1i = lane == pj ? 0.0 : zm.y;
+      wr = (d00r * z0r - d00i * z0i) + (d01r * z1r - d01i * z1i);
+      wi = (d00r * z0i + d00i * z0r) + (d01r * z1i + d01i * z1r);
+      w2r = (d01r * z0r - d01i * z0i) + (d11r * z1r - d11i * z1i);
+      w2i = (d01r * z0i + d01i * z0r) + (d11r * z1i + d11i * z1r);
+      keep = (lane == pj || lane == pm) ? 0.0 : 1.0;
+      act &= ~((1ull << pj) | (1ull << pm));
+      ++n2;
       j += 2;
+      npass = 2;
+    }
+    for (int ps = 0; ps < npass; ++ps) {
+      // multipliers of the wave's rows (broadcast reads), four at a time,
+      // the next four in flight
+      double2 ca[4], cb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ca[u] = cmp[u];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (g < 3) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cb[u] = cmp[4 * g + 4 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = 4 * g + u;
+          const double tr = fma(ca[u].x, wr, -ca[u].y * wi), ti = fma(ca[u].x, wi, ca[u].y * wr);
+          mr[t] = fma(mr[t], keep, -tr);
+          mi[t] = fma(mi[t], keep, -ti);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ca[u] = cb[u];
+      }
+      cmp = cmb;
+      wr = w2r;
+      wi = w2i;
+      keep = 1.0;
     }
     if (j < b) publish(__builtin_amdgcn_readlane(pv, j), cur ^ 1);
     cur ^= 1;
@@ -874,22 +804,15 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
   }
   // L^-1 in the pivoted order into the strict lower triangle of the tile:
   // position (a, c) is physical (pv[a], pv[c])
-  if (tid < 64) inv[pv] = lane;
-  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < CV; ++v) {
-      const int i = tr + 16 * u, c = tc + TC * v;
-      if (i < b && c < b) {
-        const int a = inv[i], cc = inv[c];
-        if (cc < a) {
-          const int64_t o = (k + a) + (int64_t)(k + cc) * n;
-          fr[o] = (T)mr[u][v];
-          fi[o] = (T)mi[u][v];
-        }
-      }
+  for (int t = 0; t < 16; ++t) {
+    const int a = __builtin_amdgcn_readlane(pos, r0 + t);
+    if (r0 + t < b && lane < b && pos < a) {
+      const int64_t o = (k + a) + (int64_t)(k + pos) * n;
+      fr[o] = (T)mr[t];
+      fi[o] = (T)mi[t];
     }
+  }
   bool bad = false;
   if (tid < b) {
     const int64_t s = f.soff + k + tid;
@@ -899,9 +822,6 @@ __global__ __launch_bounds__(NT) void k_panel(KP<T> p, int64_t first) {
     p.perm[s] = pv;
     if (!isfinite(dvr[tid]) || !isfinite(dvi[tid])) bad = true;
   }
-  // status words: [0] perturbed pivots, [1] non-finite flag, [2] 2 x 2
-  // pivots, [3] interchanges, [4] lowest domain with a perturbed or
-  // non-finite pivot (n_dom: the auxiliary matrix)
   const int where = f.dom >= 0 ? f.dom : p.n_dom;
   if (bad) {
     atomicOr(p.status + 1, 1);
@@ -2830,7 +2750,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_ASM: hipLaunchKernelGGL(k_asm<T>, g, b, 0, st, k, L.first); break;
       case L_SCAT: hipLaunchKernelGGL(k_scat<T>, g, b, 0, st, k, L.first); break;
       case L_AUXG: hipLaunchKernelGGL(k_auxg<T>, g, b, 0, st, k, L.first); break;
-      case L_PANEL: hipLaunchKernelGGL((k_panel<T, PANEL_NT>), g, dim3(PANEL_NT), 0, st, k, L.first); break;
+      case L_PANEL: hipLaunchKernelGGL(k_panel<T>, g, dim3(256), 0, st, k, L.first); break;
       case L_TRSM: hipLaunchKernelGGL(k_trsm<T>, g, b, 0, st, k, L.first); break;
       case L_SYRK: hipLaunchKernelGGL((k_syrk<T, T64>), g, b, 0, st, k, L.first); break;
       case L_SYRK2: hipLaunchKernelGGL((k_syrk<T, T128>), g, dim3(T128::NTH), 0, st, k, L.first); break;
