@@ -570,15 +570,30 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256, 4) void k_panel(KP<T> p, int64_t first) {
-  __shared__ double2 zrow[3][NB], cmrow[3][NB];
-  __shared__ double dgs[3][4];
-  __shared__ double dvr[NB], dvi[NB], dor[NB], doi[NB];
-  __shared__ int pdl[NB];
-  __shared__ double red[4];
+struct PanelSmem {
+  double2 zrow[3][NB], cmrow[3][NB];   // published rows (buffers 0 / 1: next pivot, 2: candidate)
+  double dgs[3][4];                    // their diagonal and its reciprocal
+  double dvr[NB], dvi[NB], dor[NB], doi[NB];
+  int pdl[NB];
+  double red[4];
+};
 
-  const Item it = p.items[first + blockIdx.x];
+// Pivot tile of item it (tile columns [it.k, it.k + NB)).  pend: the tile's
+// column update is pending in LDS (dst: 2 x NB rows of NB + 1, real parts
+// then imaginary parts, lower triangle, in the front's precision) and is
+// subtracted as the tile is loaded; ps may then overlay dst.
+template <typename T>
+__device__ __forceinline__ void panel_item(const KP<T> &p, const Item &it, PanelSmem &ps, const T (*dst)[NB + 1],
+                                           bool pend) {
+  double2 (&zrow)[3][NB] = ps.zrow;
+  double2 (&cmrow)[3][NB] = ps.cmrow;
+  double (&dgs)[3][4] = ps.dgs;
+  double (&dvr)[NB] = ps.dvr;
+  double (&dvi)[NB] = ps.dvi;
+  double (&dor)[NB] = ps.dor;
+  double (&doi)[NB] = ps.doi;
+  int (&pdl)[NB] = ps.pdl;
+  double (&red)[4] = ps.red;
   const FrontDev f = p.F[it.f];
   const int k = it.k, n = f.n, b = min(NB, f.s - k), tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -594,15 +609,22 @@ __global__ __launch_bounds__(256, 4) void k_panel(KP<T> p, int64_t first) {
     const int i = r0 + t;
     double xr = 0, xi = 0;
     if (i < b && lane < b) {
-      const int64_t o = (k + max(i, lane)) + (int64_t)(k + min(i, lane)) * n;
-      xr = (double)fr[o];
-      xi = (double)fi[o];
+      const int hi = max(i, lane), lo = min(i, lane);
+      const int64_t o = (k + hi) + (int64_t)(k + lo) * n;
+      T ar = fr[o], ai = fi[o];
+      if (pend) {
+        ar -= dst[hi][lo];
+        ai -= dst[NB + hi][lo];
+      }
+      xr = (double)ar;
+      xi = (double)ai;
     }
     mr[t] = xr;
     mi[t] = xi;
     amax = fmax(amax, cabs1(xr, xi));
   }
   amax = wave_max(amax);
+  if (pend) __syncthreads();   // every wave has read dst, which ps overlays
   if (lane == 0) red[w] = amax;
 
   unsigned long long act = b == 64 ? ~0ull : ((1ull << b) - 1);   // active physical rows / columns
@@ -837,6 +859,12 @@ __global__ __launch_bounds__(256, 4) void k_panel(KP<T> p, int64_t first) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_panel(KP<T> p, int64_t first) {
+  __shared__ PanelSmem ps;
+  panel_item<T>(p, p.items[first + blockIdx.x], ps, nullptr, false);
+}
+
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
 // FP32: at most 128 registers (four waves per SIMD; 164 unbounded, no
 // spills at 128).  While the side stream's Schur update fills the CUs (five
@@ -925,9 +953,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_trsm(KP<T> p, i
 // otherwise take two: 204 registers; at 128 it keeps one 8-byte value in
 // scratch, reloaded only on the ragged-tail path)
 template <typename T, class TL>
-__global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T, TL> sm;
-  const Item it = p.items[first + blockIdx.x];
+__device__ __forceinline__ void syrk_item(const KP<T> &p, const Item &it, GemmSmem<T, TL> &sm) {
   const FrontDev f = p.F[it.f];
   const int k = it.k, r0 = it.i, q0 = it.j, n = f.n;
   const int bend = min(k + KBLK, f.s);
@@ -995,6 +1021,97 @@ __global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p,
           fi[o] -= ci[x][y][i];
         }
       }
+}
+
+template <typename T, class TL>
+__global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p, int64_t first) {
+  __shared__ GemmSmem<T, TL> sm;
+  syrk_item<T, TL>(p, p.items[first + blockIdx.x], sm);
+}
+
+// Column update and pivot tile in one launch.  A pivot tile needs only the
+// diagonal block of its column update, so its workgroup computes that block
+// itself (the column update's product, staged in LDS) and factors the tile,
+// while the other workgroups update the rows below: the pivot chain no longer
+// waits for the whole column update.  Items {f, k, -1, o}: pivot tile k of
+// front f in the outer block starting at o; other items: column-update items
+// (rows below the diagonal block).
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_updpanel(KP<T> p, int64_t first) {
+  using TL = T64K32;
+  static_assert(sizeof(PanelSmem) <= sizeof(GemmSmem<T, TL>), "pivot-tile LDS inside the GEMM LDS");
+  static_assert(2 * NB * (NB + 1) * sizeof(T) <= sizeof(GemmSmem<T, TL>), "staged block inside the GEMM LDS");
+  __shared__ GemmSmem<T, TL> sm;
+  const Item it = p.items[first + blockIdx.x];
+  if (it.i >= 0) {
+    syrk_item<T, TL>(p, it, sm);
+    return;
+  }
+  const FrontDev f = p.F[it.f];
+  const int k = it.k, o = it.j, n = f.n, s = f.s, b = min(NB, s - k);
+  T *fr = p.num + f.off;
+  T *fi = fr + (int64_t)n * n;
+  const T *Wr = p.num + f.woff + ((o / KBLK) & 1) * f.wstride;   // the outer block's W buffer
+  const T *Wi = Wr + (int64_t)n * f.wcols;
+  // the column update's operands for rows [k, k + NB) and columns [k, k + b)
+  auto fa = [&](int m, int kk, T (&re)[4], T (&im)[4]) {
+    const int r = k + m;
+    const int64_t x = r + (int64_t)kk * n;
+    if (r + 3 < n) {
+      load4(fr + x, re);
+      load4(fi + x, im);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t xe = min(r + e, n - 1) + (int64_t)kk * n;
+        const T vr = fr[xe], vi = fi[xe];
+        re[e] = r + e < n ? vr : T(0);
+        im[e] = r + e < n ? vi : T(0);
+      }
+    }
+  };
+  auto fb = [&](int c, int kk, T (&re)[4], T (&im)[4]) {
+    const int q = k + c;
+    const int64_t x = q + (int64_t)(kk - o) * n;
+    if (q + 3 < k + b) {
+      load4(Wr + x, re);
+      load4(Wi + x, im);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t xe = min(q + e, k + b - 1) + (int64_t)(kk - o) * n;
+        const T vr = Wr[xe], vi = Wi[xe];
+        re[e] = q + e < k + b ? vr : T(0);
+        im[e] = q + e < k + b ? vi : T(0);
+      }
+    }
+  };
+  typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
+  gemm_tile<T, TL, false, false, 4, sizeof(T) == 4>(sm, o, k, fa, fb, cr, ci);
+  __syncthreads();   // every wave is done with the GEMM's LDS
+  T(*dst)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(&sm);
+#pragma unroll
+  for (int x = 0; x < TL::XB; ++x)
+#pragma unroll
+    for (int y = 0; y < TL::YB; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = TL::row(x), c = TL::template col<T>(y, i);
+        if (c < b && m >= c) {
+          if (m < b) {
+            dst[m][c] = cr[x][y][i];
+            dst[NB + m][c] = ci[x][y][i];
+          } else if (k + m < n) {
+            // rows past the last pivot tile's end (update rows): as the
+            // column update writes them
+            const int64_t e = (k + m) + (int64_t)(k + c) * n;
+            fr[e] -= cr[x][y][i];
+            fi[e] -= ci[x][y][i];
+          }
+        }
+      }
+  __syncthreads();
+  panel_item<T>(p, it, *reinterpret_cast<PanelSmem *>(&sm), dst, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -2755,6 +2872,7 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_SYRK: hipLaunchKernelGGL((k_syrk<T, T64>), g, b, 0, st, k, L.first); break;
       case L_SYRK2: hipLaunchKernelGGL((k_syrk<T, T128>), g, dim3(T128::NTH), 0, st, k, L.first); break;
       case L_UPD: hipLaunchKernelGGL((k_syrk<T, T64K32>), g, b, 0, st, k, L.first); break;
+      case L_UPDPANEL: hipLaunchKernelGGL(k_updpanel<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;
       case L_DINVZ: hipLaunchKernelGGL(k_dinvz<T>, g, b, 0, st, k, L.first); break;

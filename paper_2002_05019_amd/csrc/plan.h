@@ -27,6 +27,7 @@ enum LaunchKind : int32_t {
   L_JOIN,       // the main stream waits for the side stream (no kernel)
   L_DINVZ,      // Y = D^-1 Z of an interface root, stored transposed above Z
   L_STORE,      // factor columns of a front into its stored-factor place
+  L_UPDPANEL,   // column update and pivot tile in one launch (pivot-tile items first)
   // solve
   S_FINIT,      // front vector = gathered right-hand side + children updates (256 rows per item)
   S_FFIN,       // z = D^-1 y over the fully-summed rows (256 rows per item)

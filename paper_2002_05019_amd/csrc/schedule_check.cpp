@@ -35,7 +35,8 @@ using FrontAcc = std::map<int, std::vector<Acc>>;
 // Read and write sets of one launch, per front (front -1: everything).
 FrontAcc accesses(const Plan &P, const Launch &L) {
   FrontAcc out;
-  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_UPD && L.kind != L_PANEL && L.kind != L_TRSM) {
+  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_UPD && L.kind != L_PANEL && L.kind != L_TRSM &&
+      L.kind != L_UPDPANEL) {
     out[-1].push_back({SP_ALL, 0, 0, 0, 0, true});
     return out;
   }
@@ -44,7 +45,16 @@ FrontAcc accesses(const Plan &P, const Launch &L) {
     const FrontDev &d = P.fronts[it.f];
     const int n = d.n;
     std::vector<Acc> &v = out[it.f];
-    if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPD) {
+    if (L.kind == L_UPDPANEL && it.i < 0) {
+      // pivot tile k with its diagonal block's column update by the outer
+      // block starting at o; rows past a last, short tile get that update
+      const int k = it.k, o = it.j, b = std::min(NB, d.s - k);
+      const int wb = (o / KBLK) & 1 ? SP_W1 : SP_W0;
+      v.push_back({SP_A, k, std::min(k + NB, n), o, k, false});
+      v.push_back({wb, k, k + b, 0, k - o, false});
+      v.push_back({SP_A, k, std::min(k + NB, n), k, k + b, true});
+      v.push_back({SP_PIV, k, k + b, 0, 1, true});
+    } else if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPD || L.kind == L_UPDPANEL) {
       // A[r, q] -= sum_kk L[r, kk] W[q, kk - k]: a column update of the
       // pivot tile q0 (q0 inside the outer block) or a trailing tile
       const int ts = L.kind == L_SYRK2 ? 128 : 64;

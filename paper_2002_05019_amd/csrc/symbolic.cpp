@@ -1179,19 +1179,26 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     bool pending = false;
     for (int ob = 0; ob < maxt; ob += G) {
       for (int t = ob; t < ob + G && t < maxt; ++t) {
-        std::vector<Item> upd, pan, trs;
+        // the block's first tile: pivot tile alone; later tiles: one launch
+        // of the pivot tiles (each with its diagonal block's column update)
+        // followed by the column update of the rows below
+        std::vector<Item> pan, upd, trs;
         for (int f : fs) {
           const FrontDev &d = P.fronts[f];
           const int k = t * NB, o = ob * NB;
           if (k >= d.s) continue;
           const int b = std::min(NB, d.s - k);
+          pan.push_back(t > ob ? Item{f, k, -1, o} : Item{f, k, 0, 0});
           if (t > ob)
-            for (int r0 = k; r0 < d.n; r0 += GT) upd.push_back({f, o, r0, k});
-          pan.push_back({f, k, 0, 0});
+            for (int r0 = k + GT; r0 < d.n; r0 += GT) upd.push_back({f, o, r0, k});
           for (int r0 = k + b; r0 < d.n; r0 += GT) trs.push_back({f, k, r0, k - o});
         }
-        push(seq, L_UPD, upd);
-        push(seq, L_PANEL, pan);
+        if (t > ob) {
+          pan.insert(pan.end(), upd.begin(), upd.end());
+          push(seq, L_UPDPANEL, pan);
+        } else {
+          push(seq, L_PANEL, pan);
+        }
         push(seq, L_TRSM, trs);
       }
       std::vector<Item> syr[2], syr2[2];   // [0]: next block's strip, [1]: rest
