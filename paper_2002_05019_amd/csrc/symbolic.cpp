@@ -1062,6 +1062,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   // ------------------------------------------------------------ schedule
   // algorithmic flops of one work item (complex FMA = 8 real flops)
   auto item_flops = [&](int kind, const Item &it) -> double {
+    // gathers count no flops (and the assembly items of auxiliary fronts
+    // index interface blocks, not fronts)
+    if (kind == L_ASM || kind == L_SCAT || kind == L_AUXG) return 0.0;
     const FrontDev &d = P.fronts[it.f];
     const int n = d.n;
     switch (kind) {
