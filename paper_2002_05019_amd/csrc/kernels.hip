@@ -1417,8 +1417,8 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
   }
 }
 
-// z = D^-1 y on the fully-summed rows [it.i, it.i + 256) (a 2 x 2 block is
-// applied by the thread of its first row).
+// z = D^-1 y on the fully-summed rows [it.i, it.i + 256), y read from W (a
+// 2 x 2 block is applied by the thread of its first row).
 template <typename T>
 __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) {
   if (gated(p)) return;
@@ -1431,6 +1431,8 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
   if (pd < 0) return;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * p.mr;
+  const T *yr = p.num + f.woff;   // y = Z P v_s, left in W by its product
+  const T *yi = yr + (int64_t)n * f.wcols;
   const cd d = p.dinv[sa];
   const cd d1 = pd ? p.dinv[sa + 1] : cd{0, 0}, od = pd ? p.doff[sa] : cd{0, 0};
   // eight right-hand sides at a time: all loads, then the stores (the second
@@ -1440,10 +1442,10 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t o = a + (int64_t)min(j0 + q, nrhs - 1) * n;
-      y0r[q] = vr[o];
-      y0i[q] = vi[o];
-      y1r[q] = pd ? (double)vr[o + 1] : 0.0;
-      y1i[q] = pd ? (double)vi[o + 1] : 0.0;
+      y0r[q] = yr[o];
+      y0i[q] = yi[o];
+      y1r[q] = pd ? (double)yr[o + 1] : 0.0;
+      y1i[q] = pd ? (double)yi[o + 1] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1903,14 +1905,51 @@ __device__ __forceinline__ void zq_combine(T *ps, const typename V4<T>::t &P, co
     }
   }
 }
-// into the 64-output partial slot
-template <typename T>
-__device__ __forceinline__ void zq_out(T *ps, const typename V4<T>::t &P, const typename V4<T>::t &Q, T *slot,
-                                       int64_t mr, int nrhs) {
-  zq_combine<T>(ps, P, Q, nrhs, [&](int o, int q, T re, T im) {
-    slot[(int64_t)q * 64 + o] = re;
-    slot[64 * mr + (int64_t)q * 64 + o] = im;
-  });
+// The epilogue of a split product for output o (row it.i + o) and right-hand
+// side q, given its complete sum (re, im):
+//   M = 0: W = y (the diagonal-block pass reads y there)
+//   M = 1: v_R -= u
+//   M = 2: W = z - u
+//   M = 3: v(P a) = x
+template <typename T, int M>
+__device__ __forceinline__ void zq_final(const KP<T> &p, const FrontDev &f, int i0, int o, int q, T re, T im) {
+  const int n = f.n, x = i0 + o;
+  if (x >= (M == 1 ? n : f.s)) return;
+  T *vr = p.num + f.voff;
+  T *vi = vr + (int64_t)n * p.mr;
+  T *Wr = p.num + f.woff;
+  T *Wi = Wr + (int64_t)n * f.wcols;
+  const int64_t v = x + (int64_t)q * n;
+  if (M == 0) {
+    Wr[v] = re;
+    Wi[v] = im;
+  } else if (M == 1) {
+    vr[v] -= re;
+    vi[v] -= im;
+  } else if (M == 2) {
+    Wr[v] = vr[v] - re;
+    Wi[v] = vi[v] - im;
+  } else {
+    const int64_t d = (x / NB) * NB + p.perm[f.soff + x] + (int64_t)q * n;
+    vr[d] = re;
+    vi[d] = im;
+  }
+}
+// an item whose output tile has one K chunk (it.k < 0) applies the epilogue
+// itself; the others write their partial slot
+template <typename T, int M>
+__device__ __forceinline__ void zq_result(const KP<T> &p, const FrontDev &f, const Item &it, T *ps,
+                                          const typename V4<T>::t &P, const typename V4<T>::t &Q, int nrhs) {
+  if (it.k < 0) {
+    zq_combine<T>(ps, P, Q, nrhs, [&](int o, int q, T re, T im) { zq_final<T, M>(p, f, it.i, o, q, re, im); });
+  } else {
+    const int64_t mr = p.mr;
+    T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
+    zq_combine<T>(ps, P, Q, nrhs, [&](int o, int q, T re, T im) {
+      slot[(int64_t)q * 64 + o] = re;
+      slot[64 * mr + (int64_t)q * 64 + o] = im;
+    });
+  }
 }
 
 // M = 0, 1 (A(o, k) a row block of the front, contiguous along o)
@@ -1929,7 +1968,6 @@ __global__ __launch_bounds__(256) void k_zq_n(KP<T> p, int64_t first, int nrhs) 
   const T *inr = M == 0 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
   const int32_t *pm = p.perm + f.soff;
-  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
   for (int e = tid; e < ZKC * 8; e += 256) {
     const int c = e % ZKC, q = e / ZKC, cc = c0 + c;
     T br = 0, bi = 0;
@@ -1972,7 +2010,7 @@ __global__ __launch_bounds__(256) void k_zq_n(KP<T> p, int64_t first, int nrhs) 
       Q = mfma16(bv[u], in ? xi : T(0), Q);
     }
   }
-  zq_out<T>(xs, P, Q, slot, mr, nrhs);
+  zq_result<T, M>(p, f, it, xs, P, Q, nrhs);
 }
 
 // M = 2, 3 (A(o, k) a column block read along its rows k): 64 x 64 tiles of
@@ -1992,7 +2030,6 @@ __global__ __launch_bounds__(256) void k_zq_t(KP<T> p, int64_t first, int nrhs) 
   const T *fi = fr + f.lpim;
   const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
-  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
   const int m = lane & 15, kq = lane >> 4;
   typename V4<T>::t P = {0, 0, 0, 0}, Q = {0, 0, 0, 0};
   for (int rb = k0; rb < kend; rb += 64) {
@@ -2037,15 +2074,18 @@ __global__ __launch_bounds__(256) void k_zq_t(KP<T> p, int64_t first, int nrhs) 
       Q = mfma16(b, ai, Q);
     }
   }
-  zq_out<T>(&at[0][0][0], P, Q, slot, mr, nrhs);
+  zq_result<T, M>(p, f, it, &at[0][0][0], P, Q, nrhs);
 }
 
 // The same split products on the MFMA GEMM tile, for many right-hand sides
 // (64 at a time): the vector-unit kernels above re-read the front once per 8
 // columns.
-template <typename T>
-__device__ __forceinline__ void zslot_out(const typename V4<T>::t (&cr)[2][2], const typename V4<T>::t (&ci)[2][2],
-                                          T *slot, int64_t mr, int j0, int nrhs) {
+template <typename T, int M>
+__device__ __forceinline__ void zslot_out(const KP<T> &p, const FrontDev &f, const Item &it,
+                                          const typename V4<T>::t (&cr)[2][2], const typename V4<T>::t (&ci)[2][2],
+                                          int j0, int nrhs) {
+  const int64_t mr = p.mr;
+  T *slot = p.num + p.part + (int64_t)max(it.k, 0) * 128 * mr;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -2054,8 +2094,12 @@ __device__ __forceinline__ void zslot_out(const typename V4<T>::t (&cr)[2][2], c
       for (int i = 0; i < 4; ++i) {
         const int o = out_row(x), j = j0 + out_col<T>(y, i);
         if (j < nrhs) {
-          slot[(int64_t)j * 64 + o] = cr[x][y][i];
-          slot[64 * mr + (int64_t)j * 64 + o] = ci[x][y][i];
+          if (it.k < 0) {
+            zq_final<T, M>(p, f, it.i, o, j, cr[x][y][i], ci[x][y][i]);
+          } else {
+            slot[(int64_t)j * 64 + o] = cr[x][y][i];
+            slot[64 * mr + (int64_t)j * 64 + o] = ci[x][y][i];
+          }
         }
       }
 }
@@ -2077,7 +2121,6 @@ __global__ __launch_bounds__(256, 3) void k_zmma_n(KP<T> p, int64_t first, int n
   const T *inr = M == 0 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 0 ? mr : f.wcols);
   const int32_t *pm = p.perm + f.soff;
-  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
   auto fa = [&](int m, int kk, T &re, T &im) {
     const int r = i0 + m;
     if (r < rlim) {
@@ -2101,7 +2144,7 @@ __global__ __launch_bounds__(256, 3) void k_zmma_n(KP<T> p, int64_t first, int n
     };
     typename V4<T>::t cr[2][2], ci[2][2];
     gemm_tile<T, T64, false, true>(sm, c0, cend, fa, fb, cr, ci);
-    zslot_out<T>(cr, ci, slot, mr, j0, nrhs);
+    zslot_out<T, M>(p, f, it, cr, ci, j0, nrhs);
   }
 }
 
@@ -2120,7 +2163,6 @@ __global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs
   const T *fi = fr + f.lpim;
   const T *inr = M == 2 ? p.num + f.voff : p.num + f.woff;
   const T *ini = inr + (int64_t)n * (M == 2 ? mr : f.wcols);
-  T *slot = p.num + p.part + (int64_t)it.k * 128 * mr;
   auto fa = [&](int m, int kk, T &re, T &im) {
     const int col = i0 + m;
     if (col < s) {
@@ -2143,46 +2185,30 @@ __global__ __launch_bounds__(256) void k_zmma_t(KP<T> p, int64_t first, int nrhs
     };
     typename V4<T>::t cr[2][2], ci[2][2];
     gemm_tile<T, T64, true, true>(sm, k0, kend, fa, fb, cr, ci);
-    zslot_out<T>(cr, ci, slot, mr, j0, nrhs);
+    zslot_out<T, M>(p, f, it, cr, ci, j0, nrhs);
   }
 }
 
-// Reduction of the partial slots [it.k, it.k + it.j) of output tile it.i.
+// Reduction of the partial slots [it.k, it.k + it.j) of output tile it.i
+// (fixed order: deterministic), then the product's epilogue.
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) {
   if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   if (M >= 2 && skipped(p, f)) return;   // backward reductions only
-  const int n = f.n, s = f.s;
   const int64_t mr = p.mr;
-  T *vr = p.num + f.voff;
-  T *vi = vr + (int64_t)n * mr;
-  T *Wr = p.num + f.woff;
-  T *Wi = Wr + (int64_t)n * f.wcols;
   const T *part = p.num + p.part;
-  const int32_t *pm = p.perm + f.soff;
   for (int e = threadIdx.x; e < 64 * nrhs; e += 256) {
-    const int o = e & 63, j = e >> 6, x = it.i + o;
-    if (x >= (M == 1 ? n : s)) continue;
+    const int o = e & 63, j = e >> 6;
+    if (it.i + o >= (M == 1 ? f.n : f.s)) continue;
     T sr = 0, si = 0;
     for (int k = it.k; k < it.k + it.j; ++k) {
       const T *sl = part + (int64_t)k * 128 * mr + (int64_t)j * 64 + o;
       sr += sl[0];
       si += sl[64 * mr];
     }
-    const int64_t v = x + (int64_t)j * n;
-    if (M == 0) {
-      Wr[v] = sr; Wi[v] = si;
-      vr[v] = sr; vi[v] = si;
-    } else if (M == 1) {
-      vr[v] -= sr; vi[v] -= si;
-    } else if (M == 2) {
-      Wr[v] = vr[v] - sr; Wi[v] = vi[v] - si;
-    } else {
-      const int64_t d = (x / NB) * NB + pm[x] + (int64_t)j * n;
-      vr[d] = sr; vi[d] = si;
-    }
+    zq_final<T, M>(p, f, it.i, o, j, sr, si);
   }
 }
 

@@ -1357,17 +1357,24 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
 
   // solve: forward over a set of levels
   int64_t max_part = 0;
+  int ns_a = 0, ns_b = 0;   // partial slots of the level's first and second product
   auto rows = [&](std::vector<Item> &v, int f, int lo, int hi) {
     for (int r = lo; r < hi; r += 256) v.push_back({f, 0, r, 0});
   };
-  // split product: 64-output tiles [o_lo, o_hi) x K chunks [k_lo(tile), k_hi(tile)),
-  // one partial slot per item, one reduction item per tile
-  auto split = [&](std::vector<Item> &prod, std::vector<Item> &red, int f, int o_lo, int o_hi, auto k_lo,
-                   auto k_hi) {
+  // split product: 64-output tiles [o_lo, o_hi) x K chunks [k_lo(tile), k_hi(tile)).
+  // A tile with one chunk is one item that applies the epilogue itself (slot
+  // -1); a tile with several has one partial slot per item and one reduction
+  // item.
+  auto split = [&](std::vector<Item> &prod, std::vector<Item> &red, int &nslot, int f, int o_lo, int o_hi,
+                   auto k_lo, auto k_hi) {
     for (int i = o_lo; i < o_hi; i += 64) {
-      const int sbeg = (int)prod.size();
-      for (int c = k_lo(i); c < k_hi(i); c += ZKC) prod.push_back({f, (int)prod.size(), i, c});
-      red.push_back({f, sbeg, i, (int)prod.size() - sbeg});
+      if (k_hi(i) - k_lo(i) <= ZKC) {
+        prod.push_back({f, -1, i, k_lo(i)});
+        continue;
+      }
+      const int sbeg = nslot;
+      for (int c = k_lo(i); c < k_hi(i); c += ZKC) prod.push_back({f, nslot++, i, c});
+      red.push_back({f, sbeg, i, nslot - sbeg});
     }
   };
   // Small fronts: one workgroup per front.  Fronts carrying Z = L11^-1:
@@ -1388,10 +1395,11 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         }
         rows(in, f, 0, n);
         rows(fin, f, 0, s);
-        split(p0, r0, f, 0, s, [](int) { return 0; }, [&](int i) { return std::min(i + 64, s); });
-        split(p1, r1, f, s, n, [](int) { return 0; }, [&](int) { return s; });
+        split(p0, r0, ns_a, f, 0, s, [](int) { return 0; }, [&](int i) { return std::min(i + 64, s); });
+        split(p1, r1, ns_b, f, s, n, [](int) { return 0; }, [&](int) { return s; });
       }
-      max_part = std::max<int64_t>(max_part, std::max(p0.size(), p1.size()));
+      max_part = std::max<int64_t>(max_part, std::max(ns_a, ns_b));
+      ns_a = ns_b = 0;
       push(seq, S_FFRONT, small);
       push(seq, S_FINIT, in);
       push(seq, S_ZP0, p0);
@@ -1413,10 +1421,11 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
         }
         rows(in, f, s, n);
         rows(out, f, 0, s);
-        split(p2, r2, f, 0, s, [&](int) { return s; }, [&](int) { return n; });
-        split(p3, r3, f, 0, s, [](int i) { return i; }, [&](int) { return s; });
+        split(p2, r2, ns_a, f, 0, s, [&](int) { return s; }, [&](int) { return n; });
+        split(p3, r3, ns_b, f, 0, s, [](int i) { return i; }, [&](int) { return s; });
       }
-      max_part = std::max<int64_t>(max_part, std::max(p2.size(), p3.size()));
+      max_part = std::max<int64_t>(max_part, std::max(ns_a, ns_b));
+      ns_a = ns_b = 0;
       push(seq, S_BFRONT, small);
       push(seq, S_BINIT, in);
       push(seq, S_ZP2, p2);
