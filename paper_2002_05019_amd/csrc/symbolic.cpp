@@ -1276,11 +1276,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       for (auto &nd : kv.second) {
         const FrontDev &d = P.fronts[nd[0]];
         const int c0 = nd[1] * NB, m0 = nd[2] * NB, r1 = std::min(nd[3] * NB, d.s);
+        // K of a T1 item grows with its column distance, of a Z21 item with
+        // its row: each list runs over its K-determining index innermost, so
+        // that the contiguous runs handed to the XCDs carry equal work
         for (int r = m0; r < r1; r += GT)
-          for (int c = c0; c < m0; c += GT) {
-            g1.push_back({nd[0], m0, r, c});
-            g2.push_back({nd[0], m0, r, c});
-          }
+          for (int c = c0; c < m0; c += GT) g1.push_back({nd[0], m0, r, c});
+        for (int c = c0; c < m0; c += GT)
+          for (int r = m0; r < r1; r += GT) g2.push_back({nd[0], m0, r, c});
       }
       push(seq, L_ZREC1, g1);
       push(seq, L_ZREC2, g2);
