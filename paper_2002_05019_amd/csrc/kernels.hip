@@ -866,19 +866,23 @@ __global__ __launch_bounds__(256, 4) void k_panel(KP<T> p, int64_t first) {
 }
 
 // W = A21 P^T L11^-T (rows r0..r0+GT), L21 = W D^-1
-// FP32: at most 128 registers (four waves per SIMD; 164 unbounded, no
-// spills at 128).  While the side stream's Schur update fills the CUs (five
-// 96-register workgroups per SIMD), a workgroup of this size fits as soon as
-// one of them retires; at 164 it needs two retirements on one CU and waits
-// until the update has no workgroups left to hand out.
+// At most 128 registers (four waves per SIMD) and, in FP64, 16-deep K
+// stages (35 KB of LDS): while the side stream's Schur update fills the CUs
+// (FP32: five 96-register workgroups per SIMD; FP64: four 128-register, 35 KB
+// workgroups per CU), a workgroup of this size is seated as soon as one of
+// them retires; larger ones wait until the update has no workgroups left to
+// hand out.  The W tile is staged in the GEMM's LDS for the D^-1 step, in
+// FP64 in two column halves (with the neighbouring column of each, the other
+// row of a 2 x 2 pivot).
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_trsm(KP<T> p, int64_t first) {
-  __shared__ GemmSmem<T, T64K32> sm;
-  // W staging reuses the GEMM's LDS once the product is done (half the LDS
-  // of the kernel, so its workgroups find room beside the side stream's)
-  static_assert(2 * GT * (GT + 1) * sizeof(T) <= sizeof(GemmSmem<T, T64K32>), "W staging in the GEMM LDS");
-  T(*wr)[GT + 1] = reinterpret_cast<T(*)[GT + 1]>(&sm.a[0][0][0]);
-  T(*wi)[GT + 1] = wr + GT;
+__global__ __launch_bounds__(256, 4) void k_trsm(KP<T> p, int64_t first) {
+  using TL = typename std::conditional<sizeof(T) == 8, T64, T64K32>::type;
+  constexpr int HC = sizeof(T) == 8 ? 32 : GT;   // columns per staged part
+  constexpr int WS = HC + 2;                     // with one column on each side
+  __shared__ GemmSmem<T, TL> sm;
+  static_assert(2 * GT * WS * sizeof(T) <= sizeof(GemmSmem<T, TL>), "W staging in the GEMM LDS");
+  T(*wr)[WS] = reinterpret_cast<T(*)[WS]>(&sm.a[0][0][0]);
+  T(*wi)[WS] = wr + GT;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   const int k = it.k, r0 = it.i, n = f.n, b = min(NB, f.s - k);
@@ -905,8 +909,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_trsm(KP<T> p, i
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64K32, false, false, 4>(sm, 0, b, fa, fb, cr, ci);
-  __syncthreads();   // every wave is done reading the GEMM's LDS
+  gemm_tile<T, TL, false, false, 4>(sm, 0, b, fa, fb, cr, ci);
   // W buffer of the outer block starting at k - it.j
   T *Wr = p.num + f.woff + (((k - it.j) / KBLK) & 1) * f.wstride;
   T *Wi = Wr + (int64_t)n * f.wcols;
@@ -917,30 +920,45 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_trsm(KP<T> p, i
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = out_row(x), c = out_col<T>(y, i);
-        wr[m][c] = cr[x][y][i];
-        wi[m][c] = ci[x][y][i];
         if (r0 + m < n && c < b) {
           Wr[(r0 + m) + (int64_t)(it.j + c) * n] = cr[x][y][i];
           Wi[(r0 + m) + (int64_t)(it.j + c) * n] = ci[x][y][i];
         }
       }
-  __syncthreads();
-  for (int e = threadIdx.x; e < GT * b; e += 256) {
-    const int m = e % GT, c = e / GT, r = r0 + m;
-    if (r >= n) continue;
-    const int64_t s = f.soff + k + c;
-    const cd d = p.dinv[s];
-    double xr = (double)wr[m][c] * d.re - (double)wi[m][c] * d.im;
-    double xi = (double)wr[m][c] * d.im + (double)wi[m][c] * d.re;
-    const int pd = p.pdel[s];
-    if (pd) {
-      const cd o = p.doff[s];
-      const double yr = (double)wr[m][c + pd], yi = (double)wi[m][c + pd];
-      xr += yr * o.re - yi * o.im;
-      xi += yr * o.im + yi * o.re;
+  for (int c0 = 0; c0 < b; c0 += HC) {
+    __syncthreads();   // every wave is done with the GEMM's LDS / the previous part
+    // columns [c0 - 1, c0 + HC + 1) of the tile at wr[m][c - c0 + 1]
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = out_row(x), c = out_col<T>(y, i), cl = c - c0 + 1;
+          if (cl >= 0 && cl < WS) {
+            wr[m][cl] = cr[x][y][i];
+            wi[m][cl] = ci[x][y][i];
+          }
+        }
+    __syncthreads();
+    const int ce = min(b, c0 + HC);
+    for (int e = threadIdx.x; e < GT * (ce - c0); e += 256) {
+      const int m = e % GT, c = c0 + e / GT, r = r0 + m, cl = c - c0 + 1;
+      if (r >= n) continue;
+      const int64_t s = f.soff + k + c;
+      const cd d = p.dinv[s];
+      double xr = (double)wr[m][cl] * d.re - (double)wi[m][cl] * d.im;
+      double xi = (double)wr[m][cl] * d.im + (double)wi[m][cl] * d.re;
+      const int pd = p.pdel[s];
+      if (pd) {
+        const cd o = p.doff[s];
+        const double yr = (double)wr[m][cl + pd], yi = (double)wi[m][cl + pd];
+        xr += yr * o.re - yi * o.im;
+        xi += yr * o.im + yi * o.re;
+      }
+      fr[r + (int64_t)(k + c) * n] = (T)xr;
+      fi[r + (int64_t)(k + c) * n] = (T)xi;
     }
-    fr[r + (int64_t)(k + c) * n] = (T)xr;
-    fi[r + (int64_t)(k + c) * n] = (T)xi;
   }
 }
 
@@ -1038,9 +1056,13 @@ __global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p,
 // (rows below the diagonal block).
 template <typename T>
 __global__ __launch_bounds__(256, 4) void k_updpanel(KP<T> p, int64_t first) {
-  using TL = T64K32;
+  // FP64: 16-deep K stages (35 KB of LDS, like the side stream's update
+  // workgroups, so that one retirement seats a workgroup), and the diagonal
+  // block goes through the front instead of a 66 KB LDS stage
+  using TL = typename std::conditional<sizeof(T) == 8, T64, T64K32>::type;
+  constexpr bool STAGE = sizeof(T) == 4;
   static_assert(sizeof(PanelSmem) <= sizeof(GemmSmem<T, TL>), "pivot-tile LDS inside the GEMM LDS");
-  static_assert(2 * NB * (NB + 1) * sizeof(T) <= sizeof(GemmSmem<T, TL>), "staged block inside the GEMM LDS");
+  static_assert(!STAGE || 2 * NB * (NB + 1) * sizeof(T) <= sizeof(GemmSmem<T, TL>), "staged block in the GEMM LDS");
   __shared__ GemmSmem<T, TL> sm;
   const Item it = p.items[first + blockIdx.x];
   if (it.i >= 0) {
@@ -1088,6 +1110,27 @@ __global__ __launch_bounds__(256, 4) void k_updpanel(KP<T> p, int64_t first) {
   };
   typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
   gemm_tile<T, TL, false, false, 4, sizeof(T) == 4>(sm, o, k, fa, fb, cr, ci);
+  if (!STAGE) {
+    // the column update of the block's lower triangle, as the column update
+    // writes it; the tile is then loaded from the front (visible to the
+    // workgroup after the barrier)
+#pragma unroll
+    for (int x = 0; x < TL::XB; ++x)
+#pragma unroll
+      for (int y = 0; y < TL::YB; ++y)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = TL::row(x), c = TL::template col<T>(y, i);
+          if (c < b && m >= c && k + m < n) {
+            const int64_t e = (k + m) + (int64_t)(k + c) * n;
+            fr[e] -= cr[x][y][i];
+            fi[e] -= ci[x][y][i];
+          }
+        }
+    __syncthreads();
+    panel_item<T>(p, it, *reinterpret_cast<PanelSmem *>(&sm), nullptr, false);
+    return;
+  }
   __syncthreads();   // every wave is done with the GEMM's LDS
   T(*dst)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(&sm);
 #pragma unroll
