@@ -967,10 +967,8 @@ __global__ __launch_bounds__(256, 4) void k_trsm(KP<T> p, int64_t first) {
 // Trailing update (q0 >= block end): lower tiles of the trailing matrix,
 // kend = min(k + KBLK, s).  Column update (q0 < block end): the pivot tile
 // column starting at q0 receives the block's earlier tiles, kend = q0.
-// 64-edge tiles ask for four waves per SIMD (the FP64 instantiation would
-// otherwise take two: 204 registers; at 128 it keeps one 8-byte value in
-// scratch, reloaded only on the ragged-tail path)
-template <typename T, class TL>
+// G3: Gauss's three-product form of the complex product.
+template <typename T, class TL, bool G3 = (sizeof(T) == 4)>
 __device__ __forceinline__ void syrk_item(const KP<T> &p, const Item &it, GemmSmem<T, TL> &sm) {
   const FrontDev f = p.F[it.f];
   const int k = it.k, r0 = it.i, q0 = it.j, n = f.n;
@@ -1018,12 +1016,10 @@ __device__ __forceinline__ void syrk_item(const KP<T> &p, const Item &it, GemmSm
     }
   };
   typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
-  // FP32 (the refined path): the three-product form.  FP64 keeps four
-  // products: a third accumulator set does not fit its register budget, and
-  // the FP64 path is the accuracy reference.  Only this update uses it: in
-  // the interface inverses and the panel solve it moved the refined solution's
-  // global residual measurably for little time saved.
-  gemm_tile<T, TL, false, false, 4, sizeof(T) == 4>(sm, k, kend, fa, fb, cr, ci);
+  // Only the Schur update uses the three-product form: in the interface
+  // inverses and the panel solve it moved the refined solution's global
+  // residual measurably for little time saved.
+  gemm_tile<T, TL, false, false, 4, G3>(sm, k, kend, fa, fb, cr, ci);
   const bool diag = (r0 == q0);
 #pragma unroll
   for (int x = 0; x < TL::XB; ++x)
@@ -1041,10 +1037,15 @@ __device__ __forceinline__ void syrk_item(const KP<T> &p, const Item &it, GemmSm
       }
 }
 
+// The trailing update runs the three-product form in both precisions.
+// 64-edge tiles ask for four waves per SIMD in FP32 (96 registers) and three
+// in FP64 (at most 168: the third accumulator set), so that one retiring
+// workgroup seats a 128-register workgroup of the pivot chain.
 template <typename T, class TL>
-__global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? 4 : 1) void k_syrk(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(TL::NTH, TL::BM == 64 ? (sizeof(T) == 8 ? 3 : 4) : 1) void k_syrk(KP<T> p,
+                                                                                              int64_t first) {
   __shared__ GemmSmem<T, TL> sm;
-  syrk_item<T, TL>(p, p.items[first + blockIdx.x], sm);
+  syrk_item<T, TL, true>(p, p.items[first + blockIdx.x], sm);
 }
 
 // Column update and pivot tile in one launch.  A pivot tile needs only the
