@@ -300,10 +300,12 @@ enum {
     DD_KERNEL_NONE = -1,
     DD_KERNEL_SCHUR_UPDATE = 0,   /* trailing update A22 -= L21 (L21 D)^T (MFMA)   */
     DD_KERNEL_PANEL_SOLVE = 1,    /* L21 D = A21 P^T L11^-T, L21 (MFMA)            */
-    DD_KERNEL_PIVOT_TILE = 2,     /* restricted Bunch-Kaufman tile factorisation  */
+    DD_KERNEL_PIVOT_TILE = 2,     /* restricted Bunch-Kaufman tile factorisation
+                                     of the first tile of each outer block       */
     DD_KERNEL_INVERSE_UPDATE = 3, /* interface inverse X = Z^T D^-1 Z (MFMA)      */
-    DD_KERNEL_COLUMN_UPDATE = 4   /* pivot-tile columns A(:, t) -= L W^T by the
-                                     outer block's earlier tiles (MFMA)          */
+    DD_KERNEL_COLUMN_UPDATE = 4   /* the outer block's later tiles: columns
+                                     A(:, t) -= L W^T by its earlier tiles (MFMA)
+                                     and the pivot tile, in one launch           */
 };
 dd_status dd_kernel_timer_start(dd_ctx ctx, int32_t kernel);
 dd_status dd_kernel_timer_read(dd_ctx ctx, double *seconds, int64_t *launches, double *flops);

@@ -721,7 +721,7 @@ dd_status dd_get_domain_flops(dd_ctx c, int32_t dom, double *flops) {
 
 dd_status dd_kernel_timer_start(dd_ctx c, int32_t kernel) {
   if (!c) return fail(DD_ERR_ARG, "null context");
-  static const int kinds[] = {dd::L_SYRK, dd::L_TRSM, dd::L_PANEL, dd::L_INVSYRK, dd::L_UPD};
+  static const int kinds[] = {dd::L_SYRK, dd::L_TRSM, dd::L_PANEL, dd::L_INVSYRK, dd::L_UPDPANEL};
   if (kernel < -1 || kernel > 4) return fail(DD_ERR_ARG, "unknown kernel");
   if (c->tev.empty() && kernel >= 0) {
     c->tev.resize(8192);

@@ -1180,6 +1180,8 @@ __device__ __forceinline__ void zval(const T *fr, const T *fi, int n, int r, int
 //   T1  = L_true(second half rows, first half cols) Z11   -> upper triangle (transposed)
 //   Z21 = -Z22 T1                                         -> lower triangle
 // Item (f, m0, r0, c0): output tile rows [r0, r0+64), columns [c0, c0+64).
+// Both products take the three-product complex form in FP32 (in FP64 it
+// would spill at three waves per SIMD).
 // The row block is one pivot tile (r0 is a multiple of the tile size): the
 // product runs over the stored rows (contiguous, 16-byte loads) and each
 // result row is written to its true row, found from the tile's permutation
@@ -1206,7 +1208,7 @@ __global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
     zval(fr, fi, n, kk, c0 + c, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, true, 4, false, 1>(sm, c0, m0, fa, fb, cr, ci);
+  gemm_tile<T, T64, false, true, 4, sizeof(T) == 4, 1>(sm, c0, m0, fa, fb, cr, ci);
   __syncthreads();   // tr_of complete (also for an empty K range)
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -1248,7 +1250,7 @@ __global__ __launch_bounds__(256, 3) void k_zrec2(KP<T> p, int64_t first) {
     col4(fr + col, fi + col, c0 + c, m0, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, false, 4>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
+  gemm_tile<T, T64, false, false, 4, sizeof(T) == 4>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -1321,9 +1323,10 @@ __global__ __launch_bounds__(256) void k_dinvz(KP<T> p, int64_t first) {
 }
 
 // X(P a, P c) = sum_r Z(r, a) Y(r, c), Y = D^-1 Z as stored by k_dinvz;
-// lower tiles, written to both triangles
+// lower tiles, written to both triangles; three-product complex form (two
+// waves per SIMD in FP64, whose 2 x 2 accumulator sets need the registers)
 template <typename T>
-__global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_invsyrk(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -1352,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_invsyrk(KP<T> p, int64_t first) {
     }
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, true, false>(sm, a0, n, fa, fb, cr, ci);
+  gemm_tile<T, T64, true, false, 1, true>(sm, a0, n, fa, fb, cr, ci);
   T *Xr = p.num + f.xoff;
   T *Xi = Xr + (int64_t)n * n;
   const bool diag = (a0 == c0);
@@ -2941,7 +2944,6 @@ static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launc
       case L_TRSM: hipLaunchKernelGGL(k_trsm<T>, g, b, 0, st, k, L.first); break;
       case L_SYRK: hipLaunchKernelGGL((k_syrk<T, T64>), g, b, 0, st, k, L.first); break;
       case L_SYRK2: hipLaunchKernelGGL((k_syrk<T, T128>), g, dim3(T128::NTH), 0, st, k, L.first); break;
-      case L_UPD: hipLaunchKernelGGL((k_syrk<T, T64K32>), g, b, 0, st, k, L.first); break;
       case L_UPDPANEL: hipLaunchKernelGGL(k_updpanel<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC1: hipLaunchKernelGGL(k_zrec1<T>, g, b, 0, st, k, L.first); break;
       case L_ZREC2: hipLaunchKernelGGL(k_zrec2<T>, g, b, 0, st, k, L.first); break;

@@ -22,7 +22,6 @@ enum LaunchKind : int32_t {
   L_ZREC2,      // recursive inverse: Z21 = -Z22 T1
   L_INVSYRK,    // X = P^T Z^T Y P with Y = D^-1 Z
   L_SYRK2,      // trailing update on 128 x 128 tiles (512 threads)
-  L_UPD,        // column update of a pivot tile by the outer block's earlier tiles (32-deep stages)
   L_FORK,       // the side stream waits for the main stream (no kernel)
   L_JOIN,       // the main stream waits for the side stream (no kernel)
   L_DINVZ,      // Y = D^-1 Z of an interface root, stored transposed above Z

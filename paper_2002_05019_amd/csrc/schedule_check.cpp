@@ -35,7 +35,7 @@ using FrontAcc = std::map<int, std::vector<Acc>>;
 // Read and write sets of one launch, per front (front -1: everything).
 FrontAcc accesses(const Plan &P, const Launch &L) {
   FrontAcc out;
-  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_UPD && L.kind != L_PANEL && L.kind != L_TRSM &&
+  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_PANEL && L.kind != L_TRSM &&
       L.kind != L_UPDPANEL) {
     out[-1].push_back({SP_ALL, 0, 0, 0, 0, true});
     return out;
@@ -54,7 +54,7 @@ FrontAcc accesses(const Plan &P, const Launch &L) {
       v.push_back({wb, k, k + b, 0, k - o, false});
       v.push_back({SP_A, k, std::min(k + NB, n), k, k + b, true});
       v.push_back({SP_PIV, k, k + b, 0, 1, true});
-    } else if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPD || L.kind == L_UPDPANEL) {
+    } else if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPDPANEL) {
       // A[r, q] -= sum_kk L[r, kk] W[q, kk - k]: a column update of the
       // pivot tile q0 (q0 inside the outer block) or a trailing tile
       const int ts = L.kind == L_SYRK2 ? 128 : 64;

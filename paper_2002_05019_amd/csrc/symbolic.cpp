@@ -1069,7 +1069,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     const int n = d.n;
     switch (kind) {
       case L_SYRK:
-      case L_UPD: {   // C(r0.., q0..) -= L21 W^T over the lower triangle
+      case L_UPDPANEL: {   // C(r0.., q0..) -= L21 W^T over the lower triangle
+        if (kind == L_UPDPANEL && it.i < 0) {
+          // pivot tile k and its diagonal block's column update by the
+          // outer block's earlier tiles (columns it.j .. k)
+          const double b = std::min(NB, d.s - it.k);
+          return 8.0 * (b * b * b / 3.0 + b * b * b / 6.0) + 8.0 * (it.k - it.j) * b * (b + 1) / 2;
+        }
         // item: k = first column of the outer block; j = q0.  K length:
         // trailing update (i >= block end): block width; column update: q0 - k
         const int kend = std::min(it.k + KBLK, d.s);
@@ -1121,9 +1127,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     L.p0 = p0;
     L.p1 = p1;
     L.flops = 0;
-    if (kind <= L_UPD)
+    if (kind != L_FORK && kind != L_JOIN && kind < S_FINIT)
       for (const Item &it : its) L.flops += item_flops(kind, it);
-    const bool gemm = kind == L_SYRK || kind == L_SYRK2 || kind == L_UPD || kind == L_TRSM || kind == L_ZREC1 ||
+    const bool gemm = kind == L_SYRK || kind == L_SYRK2 || kind == L_TRSM || kind == L_ZREC1 ||
                       kind == L_ZREC2 || kind == L_INVSYRK;
     if (gemm && its.size() >= 16) {
       // Workgroup b runs on XCD b % 8: give each XCD a contiguous run of the
