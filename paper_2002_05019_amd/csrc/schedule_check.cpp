@@ -8,7 +8,9 @@
 // work items read and write: rectangles of a front's matrix, of its two W
 // buffers and of its pivot arrays.  Kernels other than the column / trailing
 // updates, the pivot tile and the panel solve are treated as touching
-// everything, so they must never overlap a side-stream launch.
+// everything, so they must never overlap a side-stream launch.  The work
+// items inside one launch of the pivot chain (pivot tile, column update,
+// panel solve) run concurrently too: no two of them may conflict.
 #include <algorithm>
 #include <array>
 #include <cstdio>
@@ -32,54 +34,62 @@ struct Acc {
 
 using FrontAcc = std::map<int, std::vector<Acc>>;
 
+bool tracked(int kind) {
+  return kind == L_SYRK || kind == L_SYRK2 || kind == L_PANEL || kind == L_TRSM || kind == L_UPDPANEL;
+}
+
+// Read and write sets of one work item of a tracked launch kind (all in the
+// item's front).
+void item_accesses(const Plan &P, const Launch &L, const Item &it, std::vector<Acc> &v) {
+  const FrontDev &d = P.fronts[it.f];
+  const int n = d.n;
+  if (L.kind == L_UPDPANEL && it.i < 0) {
+    // pivot tile k with its diagonal block's column update by the outer
+    // block starting at o; rows past a last, short tile get that update
+    const int k = it.k, o = it.j, b = std::min(NB, d.s - k);
+    const int wb = (o / KBLK) & 1 ? SP_W1 : SP_W0;
+    v.push_back({SP_A, k, std::min(k + NB, n), o, k, false});
+    v.push_back({wb, k, k + b, 0, k - o, false});
+    v.push_back({SP_A, k, std::min(k + NB, n), k, k + b, true});
+    v.push_back({SP_PIV, k, k + b, 0, 1, true});
+  } else if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPDPANEL) {
+    // A[r, q] -= sum_kk L[r, kk] W[q, kk - k]: a column update of the pivot
+    // tile q0 (q0 inside the outer block) or a trailing tile
+    const int ts = L.kind == L_SYRK2 ? 128 : 64;
+    const int k = it.k, r0 = it.i, q0 = it.j, bend = std::min(k + KBLK, d.s);
+    const bool colupd = q0 < bend;
+    const int kend = colupd ? q0 : bend, qend = colupd ? std::min(q0 + NB, d.s) : n;
+    const int r1 = std::min(r0 + ts, n), q1 = std::min(q0 + ts, qend);
+    const int wb = (k / KBLK) & 1 ? SP_W1 : SP_W0;
+    v.push_back({SP_A, r0, r1, k, kend, false});
+    v.push_back({wb, q0, q1, 0, kend - k, false});
+    v.push_back({SP_A, r0, r1, q0, q1, true});
+  } else if (L.kind == L_PANEL) {
+    const int k = it.k, b = std::min(NB, d.s - k);
+    v.push_back({SP_A, k, k + b, k, k + b, true});
+    v.push_back({SP_PIV, k, k + b, 0, 1, true});
+  } else {
+    // W = A21 P^T L11^-T and L21 for rows [r0, r0 + GT) of pivot tile k
+    const int k = it.k, r0 = it.i, j = it.j, b = std::min(NB, d.s - k);
+    const int r1 = std::min(r0 + GT, n);
+    const int wb = ((k - j) / KBLK) & 1 ? SP_W1 : SP_W0;
+    v.push_back({SP_A, k, k + b, k, k + b, false});
+    v.push_back({SP_PIV, k, k + b, 0, 1, false});
+    v.push_back({SP_A, r0, r1, k, k + b, true});
+    v.push_back({wb, r0, r1, j, j + b, true});
+  }
+}
+
 // Read and write sets of one launch, per front (front -1: everything).
 FrontAcc accesses(const Plan &P, const Launch &L) {
   FrontAcc out;
-  if (L.kind != L_SYRK && L.kind != L_SYRK2 && L.kind != L_PANEL && L.kind != L_TRSM &&
-      L.kind != L_UPDPANEL) {
+  if (!tracked(L.kind)) {
     out[-1].push_back({SP_ALL, 0, 0, 0, 0, true});
     return out;
   }
   for (int64_t x = 0; x < L.count; ++x) {
     const Item &it = P.items[L.first + x];
-    const FrontDev &d = P.fronts[it.f];
-    const int n = d.n;
-    std::vector<Acc> &v = out[it.f];
-    if (L.kind == L_UPDPANEL && it.i < 0) {
-      // pivot tile k with its diagonal block's column update by the outer
-      // block starting at o; rows past a last, short tile get that update
-      const int k = it.k, o = it.j, b = std::min(NB, d.s - k);
-      const int wb = (o / KBLK) & 1 ? SP_W1 : SP_W0;
-      v.push_back({SP_A, k, std::min(k + NB, n), o, k, false});
-      v.push_back({wb, k, k + b, 0, k - o, false});
-      v.push_back({SP_A, k, std::min(k + NB, n), k, k + b, true});
-      v.push_back({SP_PIV, k, k + b, 0, 1, true});
-    } else if (L.kind == L_SYRK || L.kind == L_SYRK2 || L.kind == L_UPDPANEL) {
-      // A[r, q] -= sum_kk L[r, kk] W[q, kk - k]: a column update of the
-      // pivot tile q0 (q0 inside the outer block) or a trailing tile
-      const int ts = L.kind == L_SYRK2 ? 128 : 64;
-      const int k = it.k, r0 = it.i, q0 = it.j, bend = std::min(k + KBLK, d.s);
-      const bool colupd = q0 < bend;
-      const int kend = colupd ? q0 : bend, qend = colupd ? std::min(q0 + NB, d.s) : n;
-      const int r1 = std::min(r0 + ts, n), q1 = std::min(q0 + ts, qend);
-      const int wb = (k / KBLK) & 1 ? SP_W1 : SP_W0;
-      v.push_back({SP_A, r0, r1, k, kend, false});
-      v.push_back({wb, q0, q1, 0, kend - k, false});
-      v.push_back({SP_A, r0, r1, q0, q1, true});
-    } else if (L.kind == L_PANEL) {
-      const int k = it.k, b = std::min(NB, d.s - k);
-      v.push_back({SP_A, k, k + b, k, k + b, true});
-      v.push_back({SP_PIV, k, k + b, 0, 1, true});
-    } else {
-      // W = A21 P^T L11^-T and L21 for rows [r0, r0 + GT) of pivot tile k
-      const int k = it.k, r0 = it.i, j = it.j, b = std::min(NB, d.s - k);
-      const int r1 = std::min(r0 + GT, n);
-      const int wb = ((k - j) / KBLK) & 1 ? SP_W1 : SP_W0;
-      v.push_back({SP_A, k, k + b, k, k + b, false});
-      v.push_back({SP_PIV, k, k + b, 0, 1, false});
-      v.push_back({SP_A, r0, r1, k, k + b, true});
-      v.push_back({wb, r0, r1, j, j + b, true});
-    }
+    item_accesses(P, L, it, out[it.f]);
   }
   return out;
 }
@@ -130,6 +140,23 @@ std::string check_schedule(const Plan &P, const std::vector<Launch> &seq) {
       const VC &from = L.kind == L_FORK ? clk[0] : clk[x];
       for (int i = 0; i < NS; ++i) to[i] = std::max(to[i], from[i]);
       continue;
+    }
+    if (L.kind == L_PANEL || L.kind == L_TRSM || L.kind == L_UPDPANEL) {
+      // the work items of one pivot-chain launch run concurrently
+      std::map<int, std::vector<std::vector<Acc>>> per;
+      for (int64_t x = 0; x < L.count; ++x) {
+        const Item &it = P.items[L.first + x];
+        per[it.f].emplace_back();
+        item_accesses(P, L, it, per[it.f].back());
+      }
+      for (const auto &kv : per)
+        for (size_t a = 0; a < kv.second.size(); ++a)
+          for (size_t b = a + 1; b < kv.second.size(); ++b)
+            for (const Acc &x : kv.second[a])
+              for (const Acc &y : kv.second[b])
+                if (clash(x, y))
+                  return "launch " + std::to_string(j) + " (kind " + std::to_string(L.kind) +
+                         "): work items of front " + std::to_string(kv.first) + " conflict";
     }
     const int st = L.side;
     clk[st][st]++;

@@ -35,6 +35,36 @@ struct Reader {
   }
 };
 
+// The schedule check must refuse a plan with (1) two work items of one
+// panel-solve launch writing the same rows, or (2) the main stream's wait for
+// the side stream removed.  True when both are caught (plans that do not have
+// the needed launches count as caught).
+bool planted_conflicts_caught(const dd::Plan &P) {
+  bool ok = true;
+  for (size_t j = 0; j < P.factor_seq.size(); ++j) {
+    const dd::Launch &L = P.factor_seq[j];
+    if (L.kind != dd::L_TRSM || L.count < 2 || P.items[L.first].f != P.items[L.first + 1].f) continue;
+    dd::Plan Q = P;
+    Q.items[L.first + 1].i = Q.items[L.first].i;
+    if (dd::check_schedule(Q, Q.factor_seq).empty()) {
+      std::printf("duplicated panel-solve rows in launch %zu not caught\n", j);
+      ok = false;
+    }
+    break;
+  }
+  for (size_t j = 0; j < P.factor_seq.size(); ++j) {
+    if (P.factor_seq[j].kind != dd::L_JOIN) continue;
+    dd::Plan Q = P;
+    Q.factor_seq.erase(Q.factor_seq.begin() + j);
+    if (dd::check_schedule(Q, Q.factor_seq).empty()) {
+      std::printf("missing join %zu not caught\n", j);
+      ok = false;
+    }
+    break;
+  }
+  return ok;
+}
+
 int run(const char *path) {
   FILE *f = std::fopen(path, "rb");
   if (!f) {
@@ -107,6 +137,7 @@ int run(const char *path) {
     }
     std::printf("%s (precision %d): %zu fronts, %zu factor launches\n", path, prec, P.fronts.size(),
                 P.factor_seq.size());
+    if (prec == 0 && planted_conflicts_caught(P)) std::printf("%s: planted conflicts caught\n", path);
   }
   return 0;
 }

@@ -3,8 +3,9 @@ checks of the stream schedule and the layout) built with AddressSanitizer and
 UndefinedBehaviorSanitizer and run on valid and malformed problems (no GPU).
 
 `tests/planner_check.cpp` reads problem files written here, builds the plan in
-both precisions with the schedule and layout checks, and expects malformed
-problems to be refused by the validator; any sanitizer report aborts it."""
+both precisions with the schedule and layout checks, checks that the schedule
+check refuses plans with planted conflicts, and expects malformed problems to
+be refused by the validator; any sanitizer report aborts it."""
 import os
 import shutil
 import struct
@@ -99,6 +100,8 @@ def test_planner_valid_problems(planner):
     files.append(f)
     out = _run(exe, files)
     assert out.count("factor launches") == 2 * len(files)
+    # the schedule check refuses plans with planted conflicts
+    assert out.count("planted conflicts caught") == len(files), out
 
 
 def test_planner_refuses_malformed_problems(planner):
