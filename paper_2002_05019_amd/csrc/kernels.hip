@@ -1180,15 +1180,15 @@ __device__ __forceinline__ void zval(const T *fr, const T *fi, int n, int r, int
 //   T1  = L_true(second half rows, first half cols) Z11   -> upper triangle (transposed)
 //   Z21 = -Z22 T1                                         -> lower triangle
 // Item (f, m0, r0, c0): output tile rows [r0, r0+64), columns [c0, c0+64).
-// Both products take the three-product complex form in FP32 (in FP64 it
-// would spill at three waves per SIMD).
+// Both products take the three-product complex form (FP64 at two waves per
+// SIMD: at three its accumulators would spill).
 // The row block is one pivot tile (r0 is a multiple of the tile size): the
 // product runs over the stored rows (contiguous, 16-byte loads) and each
 // result row is written to its true row, found from the tile's permutation
 // inverted in LDS.
-// three waves per SIMD (no spills at that register budget)
+// three waves per SIMD in FP32, two in FP64 (no spills at those budgets)
 template <typename T>
-__global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_zrec1(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
   __shared__ int tr_of[NB];   // stored row r0 + i holds true row r0 + tr_of[i]
   const Item it = p.items[first + blockIdx.x];
@@ -1208,7 +1208,7 @@ __global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
     zval(fr, fi, n, kk, c0 + c, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, true, 4, sizeof(T) == 4, 1>(sm, c0, m0, fa, fb, cr, ci);
+  gemm_tile<T, T64, false, true, 4, true, 1>(sm, c0, m0, fa, fb, cr, ci);
   __syncthreads();   // tr_of complete (also for an empty K range)
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -1225,9 +1225,9 @@ __global__ __launch_bounds__(256, 3) void k_zrec1(KP<T> p, int64_t first) {
       }
 }
 
-// three waves per SIMD (no spills at that register budget)
+// three waves per SIMD in FP32, two in FP64 (no spills at those budgets)
 template <typename T>
-__global__ __launch_bounds__(256, 3) void k_zrec2(KP<T> p, int64_t first) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_zrec2(KP<T> p, int64_t first) {
   __shared__ GemmSmem<T, T64> sm;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
@@ -1250,7 +1250,7 @@ __global__ __launch_bounds__(256, 3) void k_zrec2(KP<T> p, int64_t first) {
     col4(fr + col, fi + col, c0 + c, m0, re, im);
   };
   typename V4<T>::t cr[2][2], ci[2][2];
-  gemm_tile<T, T64, false, false, 4, sizeof(T) == 4>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
+  gemm_tile<T, T64, false, false, 4, true>(sm, m0, min(r0 + GT, s), fa, fb, cr, ci);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
