@@ -1016,9 +1016,8 @@ __device__ __forceinline__ void syrk_item(const KP<T> &p, const Item &it, GemmSm
     }
   };
   typename V4<T>::t cr[TL::XB][TL::YB], ci[TL::XB][TL::YB];
-  // Only the Schur update uses the three-product form: in the interface
-  // inverses and the panel solve it moved the refined solution's global
-  // residual measurably for little time saved.
+  // G3: set for the trailing update (both precisions) and for the pivot
+  // chain's column update in FP32; the panel solve keeps four products.
   gemm_tile<T, TL, false, false, 4, G3>(sm, k, kend, fa, fb, cr, ci);
   const bool diag = (r0 == q0);
 #pragma unroll
