@@ -66,7 +66,7 @@ struct dd_ctx_s {
   // correction iterations the last refined solve needed (the next one
   // enqueues as many before it synchronises)
   int refine_guess = 2;
-  // look-ahead of the factorisation: side stream and its two events
+  // side streams of the factorisation and their events
   dd::SideStream side;
   // device whose static workspace array this context is bound to (-1: a
   // caller-owned workspace)
@@ -348,15 +348,16 @@ dd_status ensure_runtime(dd_ctx_s *c) {
     c->events = true;
   }
   if (!c->cap) HIPCHECK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-  if (!c->side.stream) {
+  for (int x = 0; x < dd::N_SIDE; ++x) {
+    if (c->side.stream[x]) continue;
     hipStream_t s2;
     hipEvent_t e0, e1;
     HIPCHECK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
-    c->side.stream = s2;
-    c->side.fork = e0;
-    c->side.join = e1;
+    c->side.stream[x] = s2;
+    c->side.fork[x] = e0;
+    c->side.join[x] = e1;
   }
   return DD_OK;
 }
@@ -837,9 +838,11 @@ void dd_destroy(dd_ctx c) {
   for (auto &e : c->tev) (void)hipEventDestroy(e);
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
-  if (c->side.stream) (void)hipStreamDestroy((hipStream_t)c->side.stream);
-  for (void *e : {c->side.fork, c->side.join})
-    if (e) (void)hipEventDestroy((hipEvent_t)e);
+  for (int x = 0; x < dd::N_SIDE; ++x) {
+    if (c->side.stream[x]) (void)hipStreamDestroy((hipStream_t)c->side.stream[x]);
+    for (void *e : {c->side.fork[x], c->side.join[x]})
+      if (e) (void)hipEventDestroy((hipEvent_t)e);
+  }
   delete c;
 }
 

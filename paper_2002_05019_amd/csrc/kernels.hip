@@ -2914,19 +2914,20 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 template <typename T>
 static hipError_t run_seq(const Plan &P, const KP<T> &k, const std::vector<Launch> &seq, int nrhs, hipStream_t main,
                           KTimer *tm, const SideStream *side = nullptr) {
-  const bool two = side && side->stream;
+  const bool two = side && side->stream[0] && side->stream[1];
   for (const Launch &L : seq) {
     if (L.kind == L_FORK || L.kind == L_JOIN) {
       if (!two) continue;
-      hipEvent_t e = (hipEvent_t)(L.kind == L_FORK ? side->fork : side->join);
-      hipStream_t from = L.kind == L_FORK ? main : (hipStream_t)side->stream;
-      hipStream_t to = L.kind == L_FORK ? (hipStream_t)side->stream : main;
+      const int x = L.side - 1;
+      hipEvent_t e = (hipEvent_t)(L.kind == L_FORK ? side->fork[x] : side->join[x]);
+      hipStream_t from = L.kind == L_FORK ? main : (hipStream_t)side->stream[x];
+      hipStream_t to = L.kind == L_FORK ? (hipStream_t)side->stream[x] : main;
       hipError_t r = hipEventRecord(e, from);
       if (r == hipSuccess) r = hipStreamWaitEvent(to, e, 0);
       if (r != hipSuccess) return r;
       continue;
     }
-    hipStream_t st = two && L.side ? (hipStream_t)side->stream : main;
+    hipStream_t st = two && L.side ? (hipStream_t)side->stream[L.side - 1] : main;
     dim3 g(L.count), b(256);
     const bool timed = tm && tm->kind == (L.kind == L_SYRK2 ? (int)L_SYRK : L.kind) && tm->used + 2 <= tm->cap;
     hipEvent_t *ev = timed ? (hipEvent_t *)tm->ev : nullptr;

@@ -57,12 +57,15 @@ struct Launch {
   int32_t side = 0;  // 1: enqueued on the side stream (look-ahead of the factorisation)
 };
 
-// Side stream and the two events of the factorisation's look-ahead (owned by
-// the caller; null stream = everything on the main stream).
+// Side streams and their events of the factorisation (owned by the caller;
+// null streams = everything on the main stream).  Launch.side = s >= 1 runs
+// on stream[s - 1]: 1 the look-ahead of the trailing update, 2 the previous
+// level's inverses and stored-factor copies.
+constexpr int N_SIDE = 2;
 struct SideStream {
-  void *stream = nullptr;   // hipStream_t
-  void *fork = nullptr;     // hipEvent_t, recorded on the main stream
-  void *join = nullptr;     // hipEvent_t, recorded on the side stream
+  void *stream[N_SIDE] = {nullptr, nullptr};   // hipStream_t
+  void *fork[N_SIDE] = {nullptr, nullptr};     // hipEvent_t, recorded on the main stream
+  void *join[N_SIDE] = {nullptr, nullptr};     // hipEvent_t, recorded on the side stream
 };
 
 // Optional per-kernel event timer (diagnostics): brackets every launch of

@@ -7,8 +7,9 @@
 // launches on different streams that are not ordered, compares what their
 // work items read and write: rectangles of a front's matrix, of its two W
 // buffers and of its pivot arrays.  Kernels other than the column / trailing
-// updates, the pivot tile and the panel solve are treated as touching
-// everything, so they must never overlap a side-stream launch.  The work
+// updates, the pivot tile, the panel solve, the inverse recursion and the
+// stored-factor copy are treated as touching everything, so they must never
+// overlap a side-stream launch.  The work
 // items inside one launch of the pivot chain (pivot tile, column update,
 // panel solve) run concurrently too: no two of them may conflict.
 #include <algorithm>
@@ -35,7 +36,8 @@ struct Acc {
 using FrontAcc = std::map<int, std::vector<Acc>>;
 
 bool tracked(int kind) {
-  return kind == L_SYRK || kind == L_SYRK2 || kind == L_PANEL || kind == L_TRSM || kind == L_UPDPANEL;
+  return kind == L_SYRK || kind == L_SYRK2 || kind == L_PANEL || kind == L_TRSM || kind == L_UPDPANEL ||
+         kind == L_ZREC1 || kind == L_ZREC2 || kind == L_STORE;
 }
 
 // Read and write sets of one work item of a tracked launch kind (all in the
@@ -68,6 +70,14 @@ void item_accesses(const Plan &P, const Launch &L, const Item &it, std::vector<A
     const int k = it.k, b = std::min(NB, d.s - k);
     v.push_back({SP_A, k, k + b, k, k + b, true});
     v.push_back({SP_PIV, k, k + b, 0, 1, true});
+  } else if (L.kind == L_ZREC1 || L.kind == L_ZREC2) {
+    // Z = L11^-1 in the fully-summed block (taken whole: read and written)
+    v.push_back({SP_A, 0, n, 0, d.s, true});
+    v.push_back({SP_PIV, 0, d.s, 0, 1, false});
+  } else if (L.kind == L_STORE) {
+    // factor columns [k, k + 16) read into the stored-factor region, which
+    // no other kernel of the factorisation touches
+    v.push_back({SP_A, 0, n, it.k, std::min(it.k + 16, d.s), false});
   } else {
     // W = A21 P^T L11^-T and L21 for rows [r0, r0 + GT) of pivot tile k
     const int k = it.k, r0 = it.i, j = it.j, b = std::min(NB, d.s - k);

@@ -1315,16 +1315,39 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     push(seq, L_STORE, st);
   };
 
-  // factor
-  for (auto &lv : dom_levels) {
-    assemble(P.factor_seq, lv, false);
+  // factor.  A level's inverses (Z) and stored-factor copies run on side
+  // stream 2 beside the next level's factorisation, which touches only that
+  // level's fronts (alive together with the previous level's, so disjoint);
+  // the main stream waits for them before the level after (whose fronts may
+  // reuse their memory).  The last level, and the interface roots (whose
+  // inverses the auxiliary assembly needs), keep them on the main stream.
+  std::vector<int> prev;
+  auto side_inverse = [&](const std::vector<int> &lv) {
+    if (prev.empty()) return false;
+    sync(P.factor_seq, L_FORK, 2);
+    const size_t a = P.factor_seq.size();
+    zsteps(P.factor_seq, zset(prev));
+    store(P.factor_seq, prev);
+    for (size_t i = a; i < P.factor_seq.size(); ++i) P.factor_seq[i].side = 2;
+    prev = lv;
+    return true;
+  };
+  auto level = [&](const std::vector<int> &lv, bool aux) {
+    assemble(P.factor_seq, lv, aux);
+    const bool forked = side_inverse(lv);
     factor_steps(P.factor_seq, lv);
-    zsteps(P.factor_seq, zset(lv));
-    store(P.factor_seq, lv);
-  }
+    if (forked) sync(P.factor_seq, L_JOIN, 2);
+    prev = lv;
+  };
+  auto finish = [&]() {
+    zsteps(P.factor_seq, zset(prev));
+    store(P.factor_seq, prev);
+    prev.clear();
+  };
+  for (auto &lv : dom_levels) level(lv, false);
   if (!gam.empty()) {
-    assemble(P.factor_seq, gam, false);
-    factor_steps(P.factor_seq, gam);
+    level(gam, false);
+    prev.clear();   // the roots' inverse and X follow on the main stream
     zsteps(P.factor_seq, gam);
     std::vector<Item> sy;
     for (int f : gam) {
@@ -1336,12 +1359,8 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     push(P.factor_seq, L_DINVZ, sy);
     push(P.factor_seq, L_INVSYRK, sy);
   }
-  for (auto &lv : aux_levels) {
-    assemble(P.factor_seq, lv, true);
-    factor_steps(P.factor_seq, lv);
-    zsteps(P.factor_seq, zset(lv));
-    store(P.factor_seq, lv);
-  }
+  for (auto &lv : aux_levels) level(lv, true);
+  finish();
   P.items.resize(P.items.size() + item_pad, Item{0, 0, 0, 0});
   // tuner launches: first outer block's trailing update of every front of a
   // bucket, with both tile edges
