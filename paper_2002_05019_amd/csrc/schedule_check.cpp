@@ -70,10 +70,20 @@ void item_accesses(const Plan &P, const Launch &L, const Item &it, std::vector<A
     const int k = it.k, b = std::min(NB, d.s - k);
     v.push_back({SP_A, k, k + b, k, k + b, true});
     v.push_back({SP_PIV, k, k + b, 0, 1, true});
-  } else if (L.kind == L_ZREC1 || L.kind == L_ZREC2) {
-    // Z = L11^-1 in the fully-summed block (taken whole: read and written)
-    v.push_back({SP_A, 0, n, 0, d.s, true});
-    v.push_back({SP_PIV, 0, d.s, 0, 1, false});
+  } else if (L.kind == L_ZREC1) {
+    // split at m0: T1 = L21 Z11 for output rows [r0, r0 + GT) and columns
+    // [c0, c0 + GT), written transposed into the upper triangle
+    const int m0 = it.k, r0 = it.i, c0 = it.j, r1 = std::min(r0 + GT, d.s), c1 = std::min(c0 + GT, m0);
+    v.push_back({SP_A, r0, r1, c0, m0, false});   // stored rows of L21
+    v.push_back({SP_PIV, r0, r1, 0, 1, false});
+    v.push_back({SP_A, c0, m0, c0, c1, false});   // Z11
+    v.push_back({SP_A, c0, c1, r0, r1, true});    // T1^T
+  } else if (L.kind == L_ZREC2) {
+    // Z21 = -Z22 T1 for output rows [r0, r0 + GT) and columns [c0, c0 + GT)
+    const int m0 = it.k, r0 = it.i, c0 = it.j, r1 = std::min(r0 + GT, d.s), c1 = std::min(c0 + GT, m0);
+    v.push_back({SP_A, r0, r1, m0, r1, false});   // Z22
+    v.push_back({SP_A, c0, c1, m0, r1, false});   // T1^T
+    v.push_back({SP_A, r0, r1, c0, c1, true});    // Z21
   } else if (L.kind == L_STORE) {
     // factor columns [k, k + 16) read into the stored-factor region, which
     // no other kernel of the factorisation touches

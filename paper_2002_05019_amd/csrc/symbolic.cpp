@@ -1174,6 +1174,61 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     push(seq, kind, its);
     if (seq.size() > before) seq.back().side = side;
   };
+  // Z = L11^-1 of the fully-summed block (P basis) by recursive halving of
+  // tile ranges: a split (f, a, m, b) of tiles [a, b) at m, whose halves
+  // already hold Z, forms the lower-left block (T1 = L21 Z11, then
+  // Z21 = -Z22 T1).  All splits of one height (over all fronts) form one pair
+  // of launches.  The single tiles already hold L_kk^-1.
+  using Split = std::array<int, 4>;   // (f, a, m, b) in tiles
+  auto zlaunch = [&](std::vector<Launch> &seq, const std::map<int, std::vector<Split>> &by_h, int side) {
+    for (auto &kv : by_h) {
+      std::vector<Item> g1, g2;
+      for (auto &nd : kv.second) {
+        const FrontDev &d = P.fronts[nd[0]];
+        const int c0 = nd[1] * NB, m0 = nd[2] * NB, r1 = std::min(nd[3] * NB, d.s);
+        // K of a T1 item grows with its column distance, of a Z21 item with
+        // its row: each list runs over its K-determining index innermost, so
+        // that the contiguous runs handed to the XCDs carry equal work
+        for (int r = m0; r < r1; r += GT)
+          for (int c = c0; c < m0; c += GT) g1.push_back({nd[0], m0, r, c});
+        for (int c = c0; c < m0; c += GT)
+          for (int r = m0; r < r1; r += GT) g2.push_back({nd[0], m0, r, c});
+      }
+      push_on(seq, L_ZREC1, g1, side);
+      push_on(seq, L_ZREC2, g2, side);
+    }
+  };
+  // balanced halving of [a, b) into by_h; returns the height
+  std::function<int(std::map<int, std::vector<Split>> &, int, int, int)> zrec =
+      [&](std::map<int, std::vector<Split>> &by_h, int f, int a, int b) -> int {
+    if (b - a <= 1) return 0;
+    const int m = (a + b) / 2;
+    const int h = 1 + std::max(zrec(by_h, f, a, m), zrec(by_h, f, m, b));
+    by_h[h].push_back({f, a, m, b});
+    return h;
+  };
+  auto zsteps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
+    std::map<int, std::vector<Split>> by_h;
+    for (int f : fs) zrec(by_h, f, 0, ntiles(P.fronts[f].s, NB));
+    zlaunch(seq, by_h, 0);
+  };
+  // Z of the tiles [t0, t1) (one outer block) as soon as they are factored:
+  // their own halving, then the split (0, t0, t1) with the Z of all earlier
+  // tiles, which is complete by then (rows of Z depend only on rows of L up
+  // to them)
+  auto zblock = [&](std::vector<Launch> &seq, const std::vector<int> &fs, int t0, int tb, int side) {
+    std::map<int, std::vector<Split>> by_h;
+    int hmax = 0;
+    std::vector<Split> merge;
+    for (int f : fs) {
+      const int t1 = std::min(tb, ntiles(P.fronts[f].s, NB));
+      if (t0 >= t1) continue;
+      hmax = std::max(hmax, zrec(by_h, f, t0, t1));
+      if (t0 > 0) merge.push_back({f, 0, t0, t1});
+    }
+    if (!merge.empty()) by_h[hmax + 1] = merge;
+    zlaunch(seq, by_h, side);
+  };
   // Outer blocks of KBLK columns.  Inside a block each pivot tile gets the
   // block's earlier tiles (column update), its pivot-tile factorisation and
   // its panel solve.  The block's trailing update is split: the strip of the
@@ -1181,7 +1236,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   // stream, overlapping the next block's (latency-bound) pivot chain; the
   // main stream waits for it before the next trailing update.  Odd outer
   // blocks use the second W buffer.
-  auto factor_steps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
+  // zinc: fronts whose Z is formed block by block on side stream 2 while the
+  // following blocks are factored (the caller joins that stream).
+  auto factor_steps = [&](std::vector<Launch> &seq, const std::vector<int> &fs, const std::vector<int> &zinc) {
     int maxt = 0;
     for (int f : fs) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
     const int G = KBLK / NB;
@@ -1209,6 +1266,10 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
           push(seq, L_PANEL, pan);
         }
         push(seq, L_TRSM, trs);
+      }
+      if (!zinc.empty()) {
+        sync(seq, L_FORK, 2);
+        zblock(seq, zinc, ob, ob + G, 2);
       }
       std::vector<Item> syr[2], syr2[2];   // [0]: next block's strip, [1]: rest
       for (int f : fs) {
@@ -1264,36 +1325,6 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     push(seq, L_SCAT, sc);
     push(seq, L_AUXG, ag);
   };
-  // Z = L11^-1 of the fully-summed block (P basis) by recursive halving of
-  // the tile range; all splits of one height (over all fronts) form one pair
-  // of launches.  The single tiles already hold L_kk^-1.
-  auto zsteps = [&](std::vector<Launch> &seq, const std::vector<int> &fs) {
-    std::map<int, std::vector<std::array<int, 4>>> by_h;   // height -> (f, a, m, b) in tiles
-    std::function<int(int, int, int)> rec = [&](int f, int a, int b) -> int {
-      if (b - a <= 1) return 0;
-      const int m = (a + b) / 2;
-      const int h = 1 + std::max(rec(f, a, m), rec(f, m, b));
-      by_h[h].push_back({f, a, m, b});
-      return h;
-    };
-    for (int f : fs) rec(f, 0, ntiles(P.fronts[f].s, NB));
-    for (auto &kv : by_h) {
-      std::vector<Item> g1, g2;
-      for (auto &nd : kv.second) {
-        const FrontDev &d = P.fronts[nd[0]];
-        const int c0 = nd[1] * NB, m0 = nd[2] * NB, r1 = std::min(nd[3] * NB, d.s);
-        // K of a T1 item grows with its column distance, of a Z21 item with
-        // its row: each list runs over its K-determining index innermost, so
-        // that the contiguous runs handed to the XCDs carry equal work
-        for (int r = m0; r < r1; r += GT)
-          for (int c = c0; c < m0; c += GT) g1.push_back({nd[0], m0, r, c});
-        for (int c = c0; c < m0; c += GT)
-          for (int r = m0; r < r1; r += GT) g2.push_back({nd[0], m0, r, c});
-      }
-      push(seq, L_ZREC1, g1);
-      push(seq, L_ZREC2, g2);
-    }
-  };
   auto zfront = [&](int f) { return P.fronts[f].kind != FK_GAMMA && P.fronts[f].n > FUSE_N; };
   auto zset = [&](const std::vector<int> &lv) {
     std::vector<int> z;
@@ -1332,23 +1363,23 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     prev = lv;
     return true;
   };
-  auto level = [&](const std::vector<int> &lv, bool aux) {
+  // The interface roots have nothing after them to overlap their Z with
+  // (their X is needed at once): theirs is formed block by block beside their
+  // own factorisation instead.  (Formed that way, left to right, the top
+  // auxiliary front's Z costs the FP32 refinement accuracy: cube64j needs a
+  // fifth correction; it keeps the balanced halving at the end.)
+  auto level = [&](const std::vector<int> &lv, bool aux, const std::vector<int> &zinc) {
     assemble(P.factor_seq, lv, aux);
     const bool forked = side_inverse(lv);
-    factor_steps(P.factor_seq, lv);
-    if (forked) sync(P.factor_seq, L_JOIN, 2);
+    factor_steps(P.factor_seq, lv, zinc);
+    if (forked || !zinc.empty()) sync(P.factor_seq, L_JOIN, 2);
     prev = lv;
   };
-  auto finish = [&]() {
-    zsteps(P.factor_seq, zset(prev));
-    store(P.factor_seq, prev);
-    prev.clear();
-  };
-  for (auto &lv : dom_levels) level(lv, false);
+  const std::vector<int> none;
+  for (auto &lv : dom_levels) level(lv, false, none);
   if (!gam.empty()) {
-    level(gam, false);
-    prev.clear();   // the roots' inverse and X follow on the main stream
-    zsteps(P.factor_seq, gam);
+    level(gam, false, gam);
+    prev.clear();   // the roots' X follows on the main stream
     std::vector<Item> sy;
     for (int f : gam) {
       const FrontDev &d = P.fronts[f];
@@ -1359,8 +1390,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     push(P.factor_seq, L_DINVZ, sy);
     push(P.factor_seq, L_INVSYRK, sy);
   }
-  for (auto &lv : aux_levels) level(lv, true);
-  finish();
+  for (auto &lv : aux_levels) level(lv, true, none);
+  zsteps(P.factor_seq, zset(prev));
+  store(P.factor_seq, prev);
   P.items.resize(P.items.size() + item_pad, Item{0, 0, 0, 0});
   // tuner launches: first outer block's trailing update of every front of a
   // bucket, with both tile edges

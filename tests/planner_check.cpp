@@ -36,8 +36,8 @@ struct Reader {
 };
 
 // The schedule check must refuse a plan with (1) two work items of one
-// panel-solve launch writing the same rows, or (2) the main stream's wait for
-// the side stream removed.  True when both are caught (plans that do not have
+// panel-solve launch writing the same rows, or (2) the main stream's first
+// wait for either side stream removed.  True when both are caught (plans that do not have
 // the needed launches count as caught).
 bool planted_conflicts_caught(const dd::Plan &P) {
   bool ok = true;
@@ -52,16 +52,17 @@ bool planted_conflicts_caught(const dd::Plan &P) {
     }
     break;
   }
-  for (size_t j = 0; j < P.factor_seq.size(); ++j) {
-    if (P.factor_seq[j].kind != dd::L_JOIN) continue;
-    dd::Plan Q = P;
-    Q.factor_seq.erase(Q.factor_seq.begin() + j);
-    if (dd::check_schedule(Q, Q.factor_seq).empty()) {
-      std::printf("missing join %zu not caught\n", j);
-      ok = false;
+  for (int side = 1; side <= 2; ++side)
+    for (size_t j = 0; j < P.factor_seq.size(); ++j) {
+      if (P.factor_seq[j].kind != dd::L_JOIN || P.factor_seq[j].side != side) continue;
+      dd::Plan Q = P;
+      Q.factor_seq.erase(Q.factor_seq.begin() + j);
+      if (dd::check_schedule(Q, Q.factor_seq).empty()) {
+        std::printf("missing join %zu of side stream %d not caught\n", j, side);
+        ok = false;
+      }
+      break;
     }
-    break;
-  }
   return ok;
 }
 
