@@ -1212,21 +1212,33 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     for (int f : fs) zrec(by_h, f, 0, ntiles(P.fronts[f].s, NB));
     zlaunch(seq, by_h, 0);
   };
-  // Z of the tiles [t0, t1) (one outer block) as soon as they are factored:
-  // their own halving, then the split (0, t0, t1) with the Z of all earlier
-  // tiles, which is complete by then (rows of Z depend only on rows of L up
-  // to them)
-  auto zblock = [&](std::vector<Launch> &seq, const std::vector<int> &fs, int t0, int tb, int side) {
+  // Z of the tiles [t0, t1) (one outer block) as soon as they are factored
+  // (rows of Z depend only on rows of L up to them): their own halving, then
+  // merges in binary-counter order, so that the splits stay balanced as in
+  // the halving of the whole range: the front's completed ranges (zst, by
+  // front) are merged while the last two are equally long, and all of them
+  // after the front's last tile.
+  using ZStack = std::map<int, std::vector<std::pair<int, int>>>;
+  auto zblock = [&](std::vector<Launch> &seq, const std::vector<int> &fs, int t0, int tb, ZStack &zst, int side) {
     std::map<int, std::vector<Split>> by_h;
     int hmax = 0;
-    std::vector<Split> merge;
     for (int f : fs) {
       const int t1 = std::min(tb, ntiles(P.fronts[f].s, NB));
-      if (t0 >= t1) continue;
-      hmax = std::max(hmax, zrec(by_h, f, t0, t1));
-      if (t0 > 0) merge.push_back({f, 0, t0, t1});
+      if (t0 < t1) hmax = std::max(hmax, zrec(by_h, f, t0, t1));
     }
-    if (!merge.empty()) by_h[hmax + 1] = merge;
+    for (int f : fs) {
+      const int nt = ntiles(P.fronts[f].s, NB), t1 = std::min(tb, nt);
+      if (t0 >= t1) continue;
+      auto &st = zst[f];
+      st.push_back({t0, t1});
+      for (int h = hmax + 1; st.size() >= 2; ++h) {
+        const auto top = st.back(), below = st[st.size() - 2];
+        if (t1 < nt && top.second - top.first != below.second - below.first) break;
+        by_h[h].push_back({f, below.first, top.first, top.second});
+        st.pop_back();
+        st.back() = {below.first, top.second};
+      }
+    }
     zlaunch(seq, by_h, side);
   };
   // Outer blocks of KBLK columns.  Inside a block each pivot tile gets the
@@ -1243,6 +1255,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     for (int f : fs) maxt = std::max(maxt, ntiles(P.fronts[f].s, NB));
     const int G = KBLK / NB;
     bool pending = false;
+    ZStack zst;
     for (int ob = 0; ob < maxt; ob += G) {
       for (int t = ob; t < ob + G && t < maxt; ++t) {
         // the block's first tile: pivot tile alone; later tiles: one launch
@@ -1269,7 +1282,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       }
       if (!zinc.empty()) {
         sync(seq, L_FORK, 2);
-        zblock(seq, zinc, ob, ob + G, 2);
+        zblock(seq, zinc, ob, ob + G, zst, 2);
       }
       std::vector<Item> syr[2], syr2[2];   // [0]: next block's strip, [1]: rest
       for (int f : fs) {
@@ -1365,9 +1378,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   };
   // The interface roots have nothing after them to overlap their Z with
   // (their X is needed at once): theirs is formed block by block beside their
-  // own factorisation instead.  (Formed that way, left to right, the top
-  // auxiliary front's Z costs the FP32 refinement accuracy: cube64j needs a
-  // fifth correction; it keeps the balanced halving at the end.)
+  // own factorisation instead.  The top auxiliary front keeps the halving
+  // after its factorisation: beside its latency-bound chain the merges slow
+  // the chain as much as they save, and the final merge is long.
   auto level = [&](const std::vector<int> &lv, bool aux, const std::vector<int> &zinc) {
     assemble(P.factor_seq, lv, aux);
     const bool forked = side_inverse(lv);
