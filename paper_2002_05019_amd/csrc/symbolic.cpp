@@ -1363,17 +1363,16 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   // stream 2 beside the next level's factorisation, which touches only that
   // level's fronts (alive together with the previous level's, so disjoint);
   // the main stream waits for them before the level after (whose fronts may
-  // reuse their memory).  The last level, and the interface roots (whose
-  // inverses the auxiliary assembly needs), keep them on the main stream.
+  // reuse their memory).  The last level keeps them on the main stream; the
+  // interface roots form their Z beside their own factorisation (below).
   std::vector<int> prev;
-  auto side_inverse = [&](const std::vector<int> &lv) {
+  auto side_inverse = [&]() {
     if (prev.empty()) return false;
     sync(P.factor_seq, L_FORK, 2);
     const size_t a = P.factor_seq.size();
     zsteps(P.factor_seq, zset(prev));
     store(P.factor_seq, prev);
     for (size_t i = a; i < P.factor_seq.size(); ++i) P.factor_seq[i].side = 2;
-    prev = lv;
     return true;
   };
   // The interface roots have nothing after them to overlap their Z with
@@ -1383,7 +1382,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   // the chain as much as they save, and the final merge is long.
   auto level = [&](const std::vector<int> &lv, bool aux, const std::vector<int> &zinc) {
     assemble(P.factor_seq, lv, aux);
-    const bool forked = side_inverse(lv);
+    const bool forked = side_inverse();
     factor_steps(P.factor_seq, lv, zinc);
     if (forked || !zinc.empty()) sync(P.factor_seq, L_JOIN, 2);
     prev = lv;
