@@ -29,19 +29,22 @@ def _current_record(tmp_path):
 
 def test_record_reported_for_its_plan(tmp_path):
     rec, path = _current_record(tmp_path)
-    got = bench.recorded_traffic("cube48", rec["schur_tile_by_front_size"], rec["launches"], path=path)
+    got = bench.recorded_traffic("cube48", rec["schur_tile_by_front_size"], rec["launches_per_factorization"], path=path)
     assert got == rec["bytes_per_launch"] > 0
 
 
 def test_record_refused_for_other_plans(tmp_path):
     rec, path = _current_record(tmp_path)
     tiles = rec["schur_tile_by_front_size"]
-    assert bench.recorded_traffic("cube48", tiles, rec["launches"] + 1, path=path) is None
-    assert bench.recorded_traffic("cube48", [128] * len(tiles), rec["launches"], path=path) is None
-    assert bench.recorded_traffic("no_such_workload", tiles, rec["launches"]) is None
+    per = rec["launches_per_factorization"]
+    assert rec["launches"] == 2 * per   # the counter run's two factorisations
+    assert bench.recorded_traffic("cube48", tiles, per + 1, path=path) is None
+    assert bench.recorded_traffic("cube48", tiles, rec["launches"], path=path) is None
+    assert bench.recorded_traffic("cube48", [128] * len(tiles), per, path=path) is None
+    assert bench.recorded_traffic("no_such_workload", tiles, per) is None
     stale = dict(rec, kernels_hip_sha256="0" * 64)
     (tmp_path / "stale.json").write_text(json.dumps(stale))
-    assert bench.recorded_traffic("cube48", tiles, rec["launches"], path=str(tmp_path / "stale.json")) is None
+    assert bench.recorded_traffic("cube48", tiles, per, path=str(tmp_path / "stale.json")) is None
 
 
 def test_more_than_one_gpu_is_refused():
