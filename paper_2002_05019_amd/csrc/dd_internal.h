@@ -47,6 +47,9 @@ struct FrontDev {
   int32_t wcols;   // columns of one W scratch buffer
   int64_t wstride; // fronts with more than one outer block: offset (T elements) of the
                    // second W buffer, used by odd outer blocks; else 0
+  int64_t uoff;    // entry of update row s in the parent-row map (rows s..n-1 follow)
+  int32_t parent;  // parent front (-1: none; then n == s)
+  int32_t upad;
 };
 
 // Work item of one workgroup; the meaning of k, i, j depends on the kernel.

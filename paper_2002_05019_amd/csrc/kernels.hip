@@ -35,6 +35,7 @@ struct KP {
   const int32_t *cfront;
   const int64_t *crmap;
   const int32_t *rmap;
+  const int32_t *urow;
   const SPair *spairs;
   const AuxItem *aux;
   const int32_t *gpos;
@@ -1387,6 +1388,21 @@ __device__ __forceinline__ bool gated(const KP<T> &p) {
   return p.skip && *(volatile const int *)p.skip != 0;
 }
 
+// Row-by-column split of a workgroup over `live` rows of a front vector: the
+// smallest power of two R >= live (at least 8, at most cap) takes the rows, and
+// the workgroup's other threads take further right-hand-side columns (thread
+// t: row t mod R, columns t / R, t / R + G, ... with G = threads / R), so the
+// small fronts of the lower levels keep the whole workgroup busy.
+struct RowSplit {
+  int r, g, G, sh;   // row offset, first column, column stride, log2(R)
+};
+__device__ __forceinline__ RowSplit row_split(int live, int cap, int threads) {
+  int sh = 3;
+  while ((1 << sh) < live && (1 << sh) < cap) ++sh;
+  const int t = threadIdx.x;
+  return RowSplit{t & ((1 << sh) - 1), t >> sh, threads >> sh, sh};
+}
+
 // ---------------------------------------------------------------------------
 // multi-RHS substitutions (front vectors v: n x mr planar, ld n)
 // Front vector rows [it.i, it.i + 256): gathered right-hand side on the
@@ -1396,7 +1412,9 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
   if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s, r = it.i + threadIdx.x;
+  const int n = f.n, s = f.s;
+  const RowSplit rs = row_split(min(256, n - it.i), 256, 256);
+  const int r = it.i + rs.r, G = rs.G;
   if (r >= n) return;
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
@@ -1423,12 +1441,13 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
       }
     ++nc;
   }
-  // eight right-hand sides at a time: all loads, then the stores
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+  // eight of this thread's right-hand sides at a time: all loads, then the
+  // stores
+  for (int j0 = rs.g; j0 < nrhs; j0 += 8 * G) {
     T xr[8], xi[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int j = min(j0 + q, nrhs - 1);
+      const int j = min(j0 + q * G, nrhs - 1);
       xr[q] = row >= 0 ? sr[row + (int64_t)j * ld] : T(0);
       xi[q] = row >= 0 ? si[row + (int64_t)j * ld] : T(0);
     }
@@ -1438,16 +1457,16 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
       const int64_t pl = (int64_t)cn[c] * mr;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int j = min(j0 + q, nrhs - 1);
+        const int j = min(j0 + q * G, nrhs - 1);
         xr[q] += cp[c][(int64_t)j * cn[c]];
         xi[q] += cp[c][(int64_t)j * cn[c] + pl];
       }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (j0 + q < nrhs) {
-        vr[r + (int64_t)(j0 + q) * n] = xr[q];
-        vi[r + (int64_t)(j0 + q) * n] = xi[q];
+      if (j0 + q * G < nrhs) {
+        vr[r + (int64_t)(j0 + q * G) * n] = xr[q];
+        vi[r + (int64_t)(j0 + q * G) * n] = xi[q];
       }
   }
   for (; ch < f.nchild; ++ch) {
@@ -1456,7 +1475,7 @@ __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs)
     const FrontDev &cf = p.F[p.cfront[f.child + ch]];
     const T *cr = p.num + cf.voff + cf.s + rr;
     const T *ci = cr + (int64_t)cf.n * mr;
-    for (int j = 0; j < nrhs; ++j) {
+    for (int j = rs.g; j < nrhs; j += G) {
       vr[r + (int64_t)j * n] += cr[(int64_t)j * cf.n];
       vi[r + (int64_t)j * n] += ci[(int64_t)j * cf.n];
     }
@@ -1470,7 +1489,8 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
   if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, a = it.i + threadIdx.x;
+  const RowSplit rs = row_split(min(256, f.s - it.i), 256, 256);
+  const int n = f.n, a = it.i + rs.r, G = rs.G;
   if (a >= f.s) return;
   const int64_t sa = f.soff + a;
   const int pd = p.pdel[sa];
@@ -1481,13 +1501,13 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
   const T *yi = yr + (int64_t)n * f.wcols;
   const cd d = p.dinv[sa];
   const cd d1 = pd ? p.dinv[sa + 1] : cd{0, 0}, od = pd ? p.doff[sa] : cd{0, 0};
-  // eight right-hand sides at a time: all loads, then the stores (the second
-  // row of a 2 x 2 block is a valid row whenever pd == 1)
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+  // eight of this thread's right-hand sides at a time: all loads, then the
+  // stores (the second row of a 2 x 2 block is a valid row whenever pd == 1)
+  for (int j0 = rs.g; j0 < nrhs; j0 += 8 * G) {
     double y0r[8], y0i[8], y1r[8], y1i[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int64_t o = a + (int64_t)min(j0 + q, nrhs - 1) * n;
+      const int64_t o = a + (int64_t)min(j0 + q * G, nrhs - 1) * n;
       y0r[q] = yr[o];
       y0i[q] = yi[o];
       y1r[q] = pd ? (double)yr[o + 1] : 0.0;
@@ -1495,8 +1515,8 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      if (j0 + q >= nrhs) break;
-      const int64_t o = a + (int64_t)(j0 + q) * n;
+      if (j0 + q * G >= nrhs) break;
+      const int64_t o = a + (int64_t)(j0 + q * G) * n;
       if (pd == 0) {
         vr[o] = (T)(d.re * y0r[q] - d.im * y0i[q]);
         vi[o] = (T)(d.re * y0i[q] + d.im * y0r[q]);
@@ -1510,37 +1530,41 @@ __global__ __launch_bounds__(256) void k_ffin(KP<T> p, int64_t first, int nrhs) 
   }
 }
 
-// Update rows [it.i, it.i + 256) (>= s) of the front vector from the global
-// solution vector.
+// Update rows [it.i, it.i + 256) (>= s) of the front vector from the parent
+// front's vector, which the backward sweep has completed one level up (every
+// row of it holds the solution: fully-summed rows solved there, update rows
+// copied from its own parent); a few hundred rows per right-hand side instead
+// of a gather across the global vector.
 template <typename T>
 __global__ __launch_bounds__(256) void k_binit(KP<T> p, int64_t first, int nrhs) {
   if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   if (skipped(p, f)) return;
-  const int n = f.n, r = it.i + threadIdx.x;
+  const RowSplit rs = row_split(min(256, f.n - it.i), 256, 256);
+  const int n = f.n, r = it.i + rs.r, G = rs.G;
   if (r >= n) return;
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * mr;
-  const bool aux = f.kind == FK_AUX;
-  const int64_t ld = aux ? p.n_mult : p.n_torn;
-  const T *sr = p.num + (aux ? p.vl : p.vx);
+  const FrontDev &pf = p.F[f.parent];
+  const int64_t ld = pf.n;
+  const T *sr = p.num + pf.voff;
   const T *si = sr + ld * mr;
-  const int64_t row = f.vbase + p.vars[f.idx + r];
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+  const int64_t row = p.urow[f.uoff + r - f.s];
+  for (int j0 = rs.g; j0 < nrhs; j0 += 8 * G) {
     T xr[8], xi[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int j = min(j0 + q, nrhs - 1);
+      const int j = min(j0 + q * G, nrhs - 1);
       xr[q] = sr[row + (int64_t)j * ld];
       xi[q] = si[row + (int64_t)j * ld];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (j0 + q < nrhs) {
-        vr[r + (int64_t)(j0 + q) * n] = xr[q];
-        vi[r + (int64_t)(j0 + q) * n] = xi[q];
+      if (j0 + q * G < nrhs) {
+        vr[r + (int64_t)(j0 + q * G) * n] = xr[q];
+        vi[r + (int64_t)(j0 + q * G) * n] = xi[q];
       }
   }
 }
@@ -1553,7 +1577,8 @@ __global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) 
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
   if (skipped(p, f)) return;
-  const int n = f.n, r = it.i + threadIdx.x;
+  const RowSplit rs = row_split(min(256, f.s - it.i), 256, 256);
+  const int n = f.n, r = it.i + rs.r, G = rs.G;
   if (r >= f.s) return;
   const int64_t mr = p.mr;
   const T *vr = p.num + f.voff;
@@ -1563,19 +1588,19 @@ __global__ __launch_bounds__(256) void k_bfin(KP<T> p, int64_t first, int nrhs) 
   T *dr = p.num + (aux ? p.vl : p.vx);
   T *di = dr + ld * mr;
   const int64_t row = f.vbase + p.vars[f.idx + r];
-  for (int j0 = 0; j0 < nrhs; j0 += 8) {
+  for (int j0 = rs.g; j0 < nrhs; j0 += 8 * G) {
     T xr[8], xi[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int j = min(j0 + q, nrhs - 1);
+      const int j = min(j0 + q * G, nrhs - 1);
       xr[q] = vr[r + (int64_t)j * n];
       xi[q] = vi[r + (int64_t)j * n];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (j0 + q < nrhs) {
-        dr[row + (int64_t)(j0 + q) * ld] = xr[q];
-        di[row + (int64_t)(j0 + q) * ld] = xi[q];
+      if (j0 + q * G < nrhs) {
+        dr[row + (int64_t)(j0 + q * G) * ld] = xr[q];
+        di[row + (int64_t)(j0 + q * G) * ld] = xi[q];
       }
   }
 }
@@ -2245,9 +2270,13 @@ __global__ __launch_bounds__(256) void k_zred(KP<T> p, int64_t first, int nrhs) 
   if (M >= 2 && skipped(p, f)) return;   // backward reductions only
   const int64_t mr = p.mr;
   const T *part = p.num + p.part;
-  for (int e = threadIdx.x; e < 64 * nrhs; e += 256) {
-    const int o = e & 63, j = e >> 6;
-    if (it.i + o >= (M == 1 ? f.n : f.s)) continue;
+  const int hi = M == 1 ? f.n : f.s;
+  // rows of the tile times columns, R = 8 ... 64 rows per column
+  const RowSplit rs = row_split(min(64, hi - it.i), 64, 256);
+  const int R = 1 << rs.sh;
+  for (int e = threadIdx.x; e < R * nrhs; e += 256) {
+    const int o = e & (R - 1), j = e >> rs.sh;
+    if (it.i + o >= hi) continue;
     T sr = 0, si = 0;
     for (int k = it.k; k < it.k + it.j; ++k) {
       const T *sl = part + (int64_t)k * 128 * mr + (int64_t)j * 64 + o;
@@ -2866,6 +2895,7 @@ static KP<T> make_kp(const Plan &P, uint8_t *ws, const void *vals) {
   k.cfront = (const int32_t *)(m + P.m_cfront);
   k.crmap = (const int64_t *)(m + P.m_crmap);
   k.rmap = (const int32_t *)(m + P.m_rmap);
+  k.urow = (const int32_t *)(m + P.m_urow);
   k.spairs = (const SPair *)(m + P.m_spairs);
   k.aux = (const AuxItem *)(m + P.m_aux);
   k.gpos = (const int32_t *)(m + P.m_gpos);

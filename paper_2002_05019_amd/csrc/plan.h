@@ -103,6 +103,7 @@ struct Plan {
   std::vector<int32_t> child_front;
   std::vector<int64_t> child_rmap;
   std::vector<int32_t> rmap;
+  std::vector<int32_t> urow;   // per front: parent row of each update row (FrontDev::uoff)
   std::vector<SPair> spairs;
   std::vector<AuxItem> aux_items;
   std::vector<int32_t> gpos, gsign;
@@ -150,7 +151,7 @@ struct Plan {
   int64_t b_meta = 0, b_num = 0, b_side = 0, b_vals = 0, b_r64 = 0, b_status = 0, b_dmask = 0, b_sel = 0,
           b_total = 0;
   // offsets (bytes) of each meta array inside the meta blob
-  int64_t m_fronts, m_vars, m_cfront, m_crmap, m_rmap, m_spairs, m_aux, m_gpos, m_gsign,
+  int64_t m_fronts, m_vars, m_cfront, m_crmap, m_rmap, m_urow, m_spairs, m_aux, m_gpos, m_gsign,
       m_mrefs, m_grefs, m_hmult, m_hsign, m_rowgam, m_items, m_gemv, m_csrp, m_sellp, m_sellc, m_domrow,
       m_grep, m_gcp, m_gcr;
   std::vector<uint8_t> meta;           // serialised meta blob

@@ -632,9 +632,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
     d.wcols = std::max(NB, std::min(KBLK, (d.s + NB - 1) / NB * NB));
     if (h.kind != FK_GAMMA && d.n > FUSE_N) d.wcols = std::max<int32_t>(d.wcols, P.max_rhs);
   }
-  // children + reverse extend-add maps
+  // children + reverse extend-add maps, and each child's parent rows
   {
     std::vector<int32_t> pos;
+    for (int f = 0; f < nf; ++f) {
+      P.fronts[f].parent = -1;
+      P.fronts[f].uoff = 0;
+    }
     for (int f = 0; f < nf; ++f) {
       FrontDev &d = P.fronts[f];
       d.child = (int64_t)P.child_front.size();
@@ -648,11 +652,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
       pos.assign((size_t)maxv + 1, -1);
       for (int r = 0; r < d.n; ++r) pos[fv[r]] = r;
       for (int c : F[f].kids) {
-        const FrontDev &cd = P.fronts[c];
+        FrontDev &cd = P.fronts[c];
         P.child_front.push_back(c);
         P.child_rmap.push_back((int64_t)P.rmap.size());
         size_t base = P.rmap.size();
         P.rmap.resize(base + d.n, -1);
+        cd.parent = f;
+        cd.uoff = (int64_t)P.urow.size();
         const int32_t *cv = &P.vars[cd.idx];
         int prev = -1;
         for (int j = cd.s; j < cd.n; ++j) {
@@ -662,9 +668,13 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
           if (pp <= prev) return "internal: extend-add map not monotone";
           prev = pp;
           P.rmap[base + pp] = j - cd.s;
+          P.urow.push_back(pp);
         }
       }
     }
+    for (int f = 0; f < nf; ++f)
+      if (P.fronts[f].n > P.fronts[f].s && P.fronts[f].parent < 0)
+        return "internal: update rows without a parent front";
   }
 
   // ------------------------------------------------------------ original entries (domain fronts)
@@ -1536,6 +1546,7 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
   P.m_cfront = put(P.child_front.data(), P.child_front.size() * 4);
   P.m_crmap = put(P.child_rmap.data(), P.child_rmap.size() * 8);
   P.m_rmap = put(P.rmap.data(), P.rmap.size() * 4);
+  P.m_urow = put(P.urow.data(), P.urow.size() * 4);
   P.m_spairs = put(P.spairs.data(), P.spairs.size() * sizeof(SPair));
   P.m_aux = put(P.aux_items.data(), P.aux_items.size() * sizeof(AuxItem));
   P.m_gpos = put(P.gpos.data(), P.gpos.size() * 4);
