@@ -229,6 +229,26 @@ std::string check_layout(const Plan &P) {
   if (!m.empty()) return m;
   for (auto &x : st)
     if (x.first.first < 0 || x.first.second > P.e_stored) return "layout: stored factor outside its region";
+  // the backward sweep's parent-row map inverts the parent's extend-add map:
+  // update row j of child c sits in row urow[c.uoff + j - c.s] of its parent,
+  // whose map sends that row back to j - c.s
+  for (int p = 0; p < nf; ++p) {
+    const FrontDev &d = P.fronts[p];
+    for (int ch = 0; ch < d.nchild; ++ch) {
+      const int c = P.child_front[d.child + ch];
+      const FrontDev &cd = P.fronts[c];
+      if (cd.parent != p) return "layout: child " + std::to_string(c) + " names another parent";
+      const int64_t rb = P.child_rmap[d.child + ch];
+      if (cd.uoff < 0 || cd.uoff + (cd.n - cd.s) > (int64_t)P.urow.size()) return "layout: parent-row map out of range";
+      for (int j = cd.s; j < cd.n; ++j) {
+        const int32_t pp = P.urow[cd.uoff + j - cd.s];
+        if (pp < 0 || pp >= d.n || P.rmap[rb + pp] != j - cd.s)
+          return "layout: parent-row map of front " + std::to_string(c) + " does not invert the extend-add map";
+      }
+    }
+  }
+  for (int f = 0; f < nf; ++f)
+    if (P.fronts[f].n > P.fronts[f].s && P.fronts[f].parent < 0) return "layout: update rows without a parent";
   int nlev = 0;
   for (int f = 0; f < nf; ++f) nlev = std::max(nlev, P.front_last[f] + 1);
   for (int l = 0; l < nlev; ++l) {

@@ -35,9 +35,10 @@ struct Reader {
   }
 };
 
-// The schedule check must refuse a plan with (1) two work items of one
-// panel-solve launch writing the same rows, or (2) the main stream's first
-// wait for either side stream removed.  True when both are caught (plans that do not have
+// The schedule and layout checks must refuse a plan with (1) two work items
+// of one panel-solve launch writing the same rows, (2) the main stream's first
+// wait for either side stream removed, or (3) a wrong row in the backward
+// sweep's parent-row map.  True when all are caught (plans that do not have
 // the needed launches count as caught).
 bool planted_conflicts_caught(const dd::Plan &P) {
   bool ok = true;
@@ -63,6 +64,19 @@ bool planted_conflicts_caught(const dd::Plan &P) {
       }
       break;
     }
+  // (3) an update row of the backward sweep's parent-row map pointed at the
+  // parent's next row
+  for (size_t c = 0; c < P.fronts.size(); ++c) {
+    const dd::FrontDev &cd = P.fronts[c];
+    if (cd.parent < 0 || cd.n <= cd.s) continue;
+    dd::Plan Q = P;
+    Q.urow[cd.uoff] += 1;
+    if (dd::check_layout(Q).empty()) {
+      std::printf("shifted parent row of front %zu not caught\n", c);
+      ok = false;
+    }
+    break;
+  }
   return ok;
 }
 
