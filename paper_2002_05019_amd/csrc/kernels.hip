@@ -1406,16 +1406,18 @@ __device__ __forceinline__ RowSplit row_split(int live, int cap, int threads) {
 // ---------------------------------------------------------------------------
 // multi-RHS substitutions (front vectors v: n x mr planar, ld n)
 // Front vector rows [it.i, it.i + 256): gathered right-hand side on the
-// fully-summed rows plus the children's update parts (extend-add).
+// fully-summed rows plus the children's update parts (extend-add).  A front
+// without children gets its fully-summed rows only: its forward product
+// writes the update rows outright.
 template <typename T>
 __global__ __launch_bounds__(256) void k_finit(KP<T> p, int64_t first, int nrhs) {
   if (gated(p)) return;
   const Item it = p.items[first + blockIdx.x];
   const FrontDev f = p.F[it.f];
-  const int n = f.n, s = f.s;
-  const RowSplit rs = row_split(min(256, n - it.i), 256, 256);
+  const int n = f.n, s = f.s, hi = f.nchild ? n : s;
+  const RowSplit rs = row_split(min(256, hi - it.i), 256, 256);
   const int r = it.i + rs.r, G = rs.G;
-  if (r >= n) return;
+  if (r >= hi) return;
   const int64_t mr = p.mr;
   T *vr = p.num + f.voff;
   T *vi = vr + (int64_t)n * mr;
@@ -1995,8 +1997,11 @@ __device__ __forceinline__ void zq_final(const KP<T> &p, const FrontDev &f, int 
     Wr[v] = re;
     Wi[v] = im;
   } else if (M == 1) {
-    vr[v] -= re;
-    vi[v] -= im;
+    // a front without children has no extend-add sums in its update rows
+    // (the gather left them alone): 0 - u, as if a zero had been stored
+    const T br = f.nchild ? vr[v] : T(0), bi = f.nchild ? vi[v] : T(0);
+    vr[v] = br - re;
+    vi[v] = bi - im;
   } else if (M == 2) {
     Wr[v] = vr[v] - re;
     Wi[v] = vi[v] - im;

@@ -1474,7 +1474,9 @@ std::string build_plan(const ProblemView &p, const SetupOptions &o, Plan &P) {
           small.push_back({f, 0, 0, 0});
           continue;
         }
-        rows(in, f, 0, n);
+        // without children the update rows hold no extend-add sums: the
+        // forward product writes them outright
+        rows(in, f, 0, d.nchild ? n : s);
         rows(fin, f, 0, s);
         split(p0, r0, ns_a, f, 0, s, [](int) { return 0; }, [&](int i) { return std::min(i + 64, s); });
         split(p1, r1, ns_b, f, s, n, [](int) { return 0; }, [&](int) { return s; });
